@@ -1,0 +1,174 @@
+/*
+ * gmm.h - C ABI of the MI355X (gfx950) Gaussian-mixture EM library.
+ *
+ * The library fits 3D Gaussian mixture models to point clouds by
+ * expectation-maximization and evaluates / differentiates the mixture
+ * log-likelihood of a rigidly transformed cloud.  The method is the EM of
+ * Goel, Tabib et al., "GIRA" (arXiv 2307.00071), Sec. V "Expectation
+ * Maximization": the E-step computes responsibilities (eq. 1) in the log
+ * domain (eq. 2) from the Cholesky-precision form of the Gaussian
+ * log-density (eq. 3); the M-step (named, not written out, in that
+ * section) is the standard maximum-likelihood update of weights, means and
+ * full covariances, here with a diagonal regulariser lambda.
+ *
+ * Conventions shared by every entry point
+ *  - Device pointers unless stated otherwise; every buffer is owned by the
+ *    caller.  The library keeps no per-call state besides the caller's
+ *    workspace, so calls with distinct workspaces are re-entrant.
+ *  - Points: float32, row-major N x 3 (x, y, z), no alignment requirement
+ *    beyond 4 bytes.
+ *  - Mixture: weights w[K] (float32, > 0), means mu[K][3], covariances
+ *    cov[K][3][3] (row-major; the LOWER triangle is read, a symmetric
+ *    matrix is written).
+ *  - All work is enqueued on `stream` (a hipStream_t; NULL = the legacy
+ *    default stream).  Host-side argument errors return before anything is
+ *    enqueued.  Device-side conditions (a covariance that is not SPD, a
+ *    non-finite point or result, a label out of range) are collected in a
+ *    status word inside the workspace; entry points that synchronise
+ *    return it, the others leave it for gmm_workspace_status().
+ *  - Workspace: `ws` is a device buffer of at least the size reported by
+ *    the matching *_workspace_size() call, aligned to 256 bytes.  With
+ *    ws == NULL the library allocates one stream-ordered (hipMallocAsync)
+ *    and frees it after the call.
+ *  - Limits: 1 <= K <= GMM_MAX_K, 1 <= N <= GMM_MAX_N, K <= N for fits.
+ */
+#ifndef GMM_MI355X_H
+#define GMM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GMM_MAX_K 1024
+#define GMM_MAX_N ((int64_t)1 << 31)
+
+typedef enum {
+    GMM_OK = 0,
+    GMM_ERR_INVALID_ARG = 1,   /* bad size, NULL pointer, label or option  */
+    GMM_ERR_NOT_SPD = 2,       /* a covariance has a non-positive pivot    */
+    GMM_ERR_NONFINITE = 3,     /* NaN/Inf in the points or in a result     */
+    GMM_ERR_OOM = 4,           /* workspace too small / allocation failed  */
+    GMM_ERR_DEVICE = 5,        /* a HIP runtime call failed                */
+    GMM_ERR_UNSUPPORTED = 6    /* a size above the compiled limits         */
+} gmm_status;
+
+/* Second-moment accumulation of the M-step.
+ *  SHIFTED:  one pass; the E-step's own offsets d = x - mu_old (exact in
+ *            FP32 for points near the component) are accumulated as
+ *            sum g, sum g d, sum g d d^T (FP32 products, FP64 sums) and
+ *            re-centred on the new mean in FP64.
+ *  TWO_PASS: a first pass gives the new mean, a second pass (re-deriving
+ *            the same responsibilities) accumulates the scatter about it;
+ *            twice the E-step work, no re-centring error.                  */
+enum { GMM_MOMENTS_SHIFTED = 0, GMM_MOMENTS_TWO_PASS = 1 };
+
+/* flags */
+#define GMM_FLAG_ASYNC 1u   /* do not synchronise; read the status later  */
+
+typedef struct {
+    int32_t iters;        /* T >= 0 EM iterations (E-step + M-step each)   */
+    double reg_covar;     /* lambda >= 0, added to every covariance diagonal
+                             after each M-step                             */
+    int32_t moment_mode;  /* GMM_MOMENTS_*                                 */
+    uint32_t flags;       /* GMM_FLAG_*                                    */
+} gmm_fit_opts;
+
+/* Short text of a status code (static storage). */
+const char *gmm_status_string(gmm_status s);
+
+/* Text of the last host-side error detected in this thread (static,
+ * thread-local; "" when none). */
+const char *gmm_last_error(void);
+
+/* Waits for `stream` and returns the device status word of a workspace
+ * used by a previous call (GMM_OK when no device-side error was seen). */
+gmm_status gmm_workspace_status(const void *ws, void *stream);
+
+/* ---------------------------------------------------------------- fitting
+ * gmm_fit: fixed-iteration EM (Sec. V "Expectation Maximization").
+ *  pts          device float32 N x 3.
+ *  init_labels  device int32 N with values in [0, K), or NULL.  Non-NULL:
+ *               theta_0 is the M-step of the one-hot responsibilities these
+ *               labels define (the responsibility matrix a k-means style
+ *               initialisation hands to EM, Sec. V fig. "information
+ *               flow") and w/mu/cov are outputs only.  NULL: w/mu/cov hold
+ *               theta_0 on entry.
+ *  w, mu, cov   device float32 K, K x 3, K x 3 x 3; theta_T on return.
+ *  loglik       device float64 array of iters + 1 entries, or NULL:
+ *               loglik[t] = sum_n ln sum_b pi_b N(x_n | mu_b, Sigma_b) at
+ *               theta_t (nats; eq. 2 normaliser summed over the points);
+ *               loglik[iters] is evaluated at the returned parameters.
+ *  Each iteration: E-step with theta_t (FP32 arithmetic, eq. 1-3), M-step
+ *  N_b = sum_n g_nb + 10*DBL_EPSILON, pi_b = N_b / sum_a N_a,
+ *  mu_b = sum_n g_nb x_n / N_b,
+ *  Sigma_b = sum_n g_nb (x_n - mu_b)(x_n - mu_b)^T / N_b + lambda I
+ *  (FP64 sums), then an FP64 Cholesky of each Sigma_b for the next E-step.
+ *  Synchronises `stream` once at the end unless GMM_FLAG_ASYNC is set.
+ *  Errors: INVALID_ARG (sizes, NULL pointers, options), UNSUPPORTED
+ *  (K > GMM_MAX_K), OOM (workspace), then device-side NOT_SPD / NONFINITE /
+ *  INVALID_ARG (label out of range). */
+size_t gmm_fit_workspace_size(int64_t n, int32_t k, const gmm_fit_opts *opts);
+
+gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
+                   const int32_t *init_labels, float *w, float *mu, float *cov,
+                   double *loglik, const gmm_fit_opts *opts, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/* --------------------------------------------------------- log-likelihood
+ * gmm_loglik: L = sum_n ln sum_b pi_b N(y_n | mu_b, Sigma_b) with
+ * y_n = R(omega) x_n + t (eq. 2-3 applied to the transformed cloud).
+ *  pose6    device float32 (omega_x, omega_y, omega_z, t_x, t_y, t_z) with
+ *           R = exp([omega]_x) (axis-angle), or NULL for the identity.
+ *  w        used as given (no renormalisation); must be > 0.
+ *  out_L    device float64 scalar.
+ *  out_lse  device float32 N (per-point ln sum_b pi_b N(y_n|.)), or NULL;
+ *           pass it to gmm_loglik_backward to skip one E-step.
+ *  Does not synchronise.  Errors: host-side as gmm_fit; device-side
+ *  NOT_SPD / NONFINITE via gmm_workspace_status(). */
+size_t gmm_loglik_workspace_size(int64_t n, int32_t k);
+
+gmm_status gmm_loglik(const float *pts, int64_t n, const float *pose6,
+                      int32_t k, const float *w, const float *mu,
+                      const float *cov, double *out_L, float *out_lse,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* gmm_loglik_backward: gradient of grad_L * L (the inputs as gmm_loglik).
+ *  lse      device float32 N from gmm_loglik on the same inputs, or NULL
+ *           (then it is recomputed).
+ *  grad_L   device float64 scalar (the upstream gradient), or NULL for 1.
+ *  Outputs (device float32, any may be NULL):
+ *   g_pose6  6: (dL/domega, dL/dt), omega through the SO(3) left Jacobian;
+ *   g_pts    N x 3: dL/dx_n = R^T g_n, g_n = -sum_b gamma_nb Sigma_b^-1 d_nb;
+ *   g_w      K: N_b / pi_b (weights treated as free parameters);
+ *   g_mu     K x 3: Sigma_b^-1 sum_n gamma_nb d_nb;
+ *   g_cov    K x 3 x 3: 1/2 Sigma_b^-1 (sum_n gamma_nb d d^T) Sigma_b^-1
+ *            - 1/2 N_b Sigma_b^-1 (the symmetric gradient);
+ *  with d_nb = y_n - mu_b and N_b = sum_n gamma_nb.  Does not synchronise. */
+size_t gmm_loglik_backward_workspace_size(int64_t n, int32_t k);
+
+gmm_status gmm_loglik_backward(const float *pts, int64_t n, const float *pose6,
+                               int32_t k, const float *w, const float *mu,
+                               const float *cov, const float *lse,
+                               const double *grad_L, float *g_pose6,
+                               float *g_pts, float *g_w, float *g_mu,
+                               float *g_cov, void *ws, size_t ws_bytes,
+                               void *stream);
+
+/* ------------------------------------------------------------ profiling
+ * Kernel timing for benchmarks.  While enabled (per calling host thread),
+ * every E+M statistics launch of the tile kernel made by gmm_fit is
+ * bracketed by two HIP events recorded on the caller's stream.
+ * gmm_profile_read waits for the recorded events, returns the summed
+ * kernel time (ms) and the launch count since the last read, and resets
+ * them.  Errors: DEVICE when an event call fails. */
+gmm_status gmm_profile_enable(int on);
+gmm_status gmm_profile_read(double *tile_ms_total, int64_t *tile_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMM_MI355X_H */

@@ -1,0 +1,208 @@
+"""MI355X-native GMM EM fitting and differentiable GMM registration likelihood.
+
+Thin PyTorch-facing layer over the HIP library ``libgmm.so`` (C ABI in
+include/gmm.h).  PyTorch provides device memory and the current stream;
+every arithmetic step runs in the library's kernels.
+
+The method is the EM of GIRA (arXiv 2307.00071), Sec. V "Expectation
+Maximization" (eq. 1-3), with the standard full-covariance M-step.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+
+__all__ = ["fit", "loglik", "loglik_backward", "GMMLogLik", "FitResult"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_points(points):
+    torch = _torch()
+    if not isinstance(points, torch.Tensor) or not points.is_cuda:
+        raise TypeError("points must be a CUDA (HIP) torch tensor")
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must be float32 of shape (N, 3)")
+    return points.contiguous()
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+class FitResult:
+    """Parameters theta_T (float32) and the log-likelihood history (float64,
+    iters + 1 entries, L(theta_t) in nats)."""
+
+    def __init__(self, weights, means, covariances, loglik):
+        self.weights = weights
+        self.means = means
+        self.covariances = covariances
+        self.loglik = loglik
+
+    def __iter__(self):
+        return iter((self.weights, self.means, self.covariances, self.loglik))
+
+
+def fit(points, k, iters=100, reg_covar=1e-3, labels=None, theta0=None,
+        moment_mode="shifted", workspace=None, sync=True):
+    """EM fit of a K-component 3D GMM to ``points`` (float32 (N, 3), on GPU).
+
+    Start either from hard ``labels`` (int32 (N,), values in [0, K)) whose
+    one-hot M-step gives theta_0, or from ``theta0 = (w, mu, cov)``."""
+    torch = _torch()
+    lib = _lib.load()
+    pts = _check_points(points)
+    dev = pts.device
+    n = pts.shape[0]
+    opts = _lib.FitOpts(int(iters), float(reg_covar),
+                        {"shifted": _lib.GMM_MOMENTS_SHIFTED,
+                         "two_pass": _lib.GMM_MOMENTS_TWO_PASS}[moment_mode],
+                        0 if sync else _lib.GMM_FLAG_ASYNC)
+    if labels is not None:
+        lab = labels.to(device=dev, dtype=torch.int32).contiguous()
+        if lab.shape != (n,):
+            raise ValueError("labels must have shape (N,)")
+        w = torch.empty(k, dtype=torch.float32, device=dev)
+        mu = torch.empty(k, 3, dtype=torch.float32, device=dev)
+        cov = torch.empty(k, 3, 3, dtype=torch.float32, device=dev)
+    elif theta0 is not None:
+        lab = None
+        w = theta0[0].to(device=dev, dtype=torch.float32).contiguous().clone()
+        mu = theta0[1].to(device=dev, dtype=torch.float32).contiguous().clone()
+        cov = theta0[2].to(device=dev, dtype=torch.float32).contiguous().clone()
+        if w.shape != (k,) or mu.shape != (k, 3) or cov.shape != (k, 3, 3):
+            raise ValueError("theta0 shapes must be (K,), (K,3), (K,3,3)")
+    else:
+        raise ValueError("give labels or theta0")
+    L = torch.empty(iters + 1, dtype=torch.float64, device=dev)
+    need = lib.gmm_fit_workspace_size(n, k, ctypes.byref(opts))
+    if need == 0:
+        _lib.check(lib.gmm_fit(None, n, k, None, None, None, None, None,
+                               ctypes.byref(opts), None, 0, None))
+    ws = workspace if workspace is not None and workspace.numel() >= need \
+        else _workspace(need, dev)
+    st = lib.gmm_fit(_ptr(pts), n, k, _ptr(lab), _ptr(w), _ptr(mu), _ptr(cov),
+                     _ptr(L), ctypes.byref(opts), _ptr(ws), ws.numel(),
+                     _stream(dev))
+    _lib.check(st)
+    return FitResult(w, mu, cov, L)
+
+
+def fit_workspace_bytes(n, k, iters=100, reg_covar=1e-3, moment_mode="shifted"):
+    lib = _lib.load()
+    opts = _lib.FitOpts(int(iters), float(reg_covar),
+                        {"shifted": 0, "two_pass": 1}[moment_mode], 0)
+    return int(lib.gmm_fit_workspace_size(n, k, ctypes.byref(opts)))
+
+
+def _gmm_args(w, mu, cov, dev):
+    torch = _torch()
+    w = w.to(device=dev, dtype=torch.float32).contiguous()
+    mu = mu.to(device=dev, dtype=torch.float32).contiguous()
+    cov = cov.to(device=dev, dtype=torch.float32).contiguous()
+    k = w.shape[0]
+    if mu.shape != (k, 3) or cov.shape != (k, 3, 3):
+        raise ValueError("mixture shapes must be (K,), (K,3), (K,3,3)")
+    return w, mu, cov, k
+
+
+def loglik(points, w, mu, cov, pose6=None, return_lse=False):
+    """L = sum_n ln sum_b w_b N(R x_n + t | mu_b, cov_b) (float64 scalar on
+    the device).  pose6 = (omega, t) float32 (6,) or None."""
+    torch = _torch()
+    lib = _lib.load()
+    pts = _check_points(points)
+    dev = pts.device
+    n = pts.shape[0]
+    w, mu, cov, k = _gmm_args(w, mu, cov, dev)
+    pose = None if pose6 is None else pose6.to(device=dev, dtype=torch.float32).contiguous()
+    out = torch.empty((), dtype=torch.float64, device=dev)
+    lse = torch.empty(n, dtype=torch.float32, device=dev) if return_lse else None
+    need = lib.gmm_loglik_workspace_size(n, k)
+    if need == 0:
+        _lib.check(lib.gmm_loglik(None, n, None, k, None, None, None, None,
+                                  None, None, 0, None))
+    ws = _workspace(need, dev)
+    _lib.check(lib.gmm_loglik(_ptr(pts), n, _ptr(pose), k, _ptr(w), _ptr(mu),
+                              _ptr(cov), _ptr(out), _ptr(lse), _ptr(ws),
+                              ws.numel(), _stream(dev)))
+    return (out, lse) if return_lse else out
+
+
+def loglik_backward(points, w, mu, cov, pose6=None, lse=None, grad_L=None,
+                    need=("pose", "pts", "w", "mu", "cov")):
+    """Gradient of grad_L * L; returns a dict of float32 tensors."""
+    torch = _torch()
+    lib = _lib.load()
+    pts = _check_points(points)
+    dev = pts.device
+    n = pts.shape[0]
+    w, mu, cov, k = _gmm_args(w, mu, cov, dev)
+    pose = None if pose6 is None else pose6.to(device=dev, dtype=torch.float32).contiguous()
+    g = {}
+    shapes = dict(pose=(6,), pts=(n, 3), w=(k,), mu=(k, 3), cov=(k, 3, 3))
+    for key in shapes:
+        g[key] = torch.empty(shapes[key], dtype=torch.float32, device=dev) \
+            if key in need else None
+    gl = None if grad_L is None else grad_L.to(device=dev, dtype=torch.float64).contiguous()
+    lse_t = None if lse is None else lse.to(device=dev, dtype=torch.float32).contiguous()
+    nb = lib.gmm_loglik_backward_workspace_size(n, k)
+    ws = _workspace(max(nb, 256), dev)
+    _lib.check(lib.gmm_loglik_backward(
+        _ptr(pts), n, _ptr(pose), k, _ptr(w), _ptr(mu), _ptr(cov), _ptr(lse_t),
+        _ptr(gl), _ptr(g["pose"]), _ptr(g["pts"]), _ptr(g["w"]), _ptr(g["mu"]),
+        _ptr(g["cov"]), _ptr(ws), ws.numel(), _stream(dev)))
+    return g
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class GMMLogLik(torch.autograd.Function):
+        """L(points, pose6, w, mu, cov) with a hand-written backward kernel."""
+
+        @staticmethod
+        def forward(ctx, points, pose6, w, mu, cov):
+            out, lse = loglik(points, w, mu, cov, pose6=pose6, return_lse=True)
+            ctx.save_for_backward(points, pose6, w, mu, cov, lse)
+            return out
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            points, pose6, w, mu, cov, lse = ctx.saved_tensors
+            need = []
+            for key, i in (("pts", 0), ("pose", 1), ("w", 2), ("mu", 3), ("cov", 4)):
+                if ctx.needs_input_grad[i]:
+                    need.append(key)
+            g = loglik_backward(points, w, mu, cov, pose6=pose6, lse=lse,
+                                grad_L=grad_out, need=tuple(need))
+            return g["pts"], g["pose"], g["w"], g["mu"], g["cov"]
+
+    return GMMLogLik
+
+
+class _LazyAutograd:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyAutograd._cls is None:
+            _LazyAutograd._cls = _make_autograd()
+        return getattr(_LazyAutograd._cls, name)
+
+
+GMMLogLik = _LazyAutograd()

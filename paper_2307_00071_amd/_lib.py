@@ -1,0 +1,100 @@
+"""ctypes binding of libgmm.so (the C ABI declared in include/gmm.h).
+
+Only argument marshalling lives here: every step of the fit and of the
+log-likelihood runs in the HIP library.  Loading fails loudly when the
+library has not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgmm.so")
+
+GMM_OK = 0
+GMM_MOMENTS_SHIFTED = 0
+GMM_MOMENTS_TWO_PASS = 1
+GMM_FLAG_ASYNC = 1
+GMM_MAX_K = 1024
+
+EXPORTS = (
+    "gmm_status_string", "gmm_last_error", "gmm_workspace_status",
+    "gmm_fit_workspace_size", "gmm_fit",
+    "gmm_loglik_workspace_size", "gmm_loglik",
+    "gmm_loglik_backward_workspace_size", "gmm_loglik_backward",
+    "gmm_profile_enable", "gmm_profile_read",
+)
+
+
+class GmmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("gmm status %d: %s" % (status, msg))
+        self.status = status
+
+
+class FitOpts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("reg_covar", ctypes.c_double),
+                ("moment_mode", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libgmm.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            "libgmm.so is not built (%s); run `python -m "
+            "paper_2307_00071_amd.build` or __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    lib.gmm_status_string.argtypes = [ctypes.c_int]
+    lib.gmm_status_string.restype = ctypes.c_char_p
+    lib.gmm_last_error.argtypes = []
+    lib.gmm_last_error.restype = ctypes.c_char_p
+    lib.gmm_workspace_status.argtypes = [vp, vp]
+    lib.gmm_workspace_status.restype = ctypes.c_int
+    lib.gmm_fit_workspace_size.argtypes = [i64, i32, ctypes.POINTER(FitOpts)]
+    lib.gmm_fit_workspace_size.restype = sz
+    lib.gmm_fit.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp,
+                            ctypes.POINTER(FitOpts), vp, sz, vp]
+    lib.gmm_fit.restype = ctypes.c_int
+    lib.gmm_loglik_workspace_size.argtypes = [i64, i32]
+    lib.gmm_loglik_workspace_size.restype = sz
+    lib.gmm_loglik.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.gmm_loglik.restype = ctypes.c_int
+    lib.gmm_loglik_backward_workspace_size.argtypes = [i64, i32]
+    lib.gmm_loglik_backward_workspace_size.restype = sz
+    lib.gmm_loglik_backward.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp, vp,
+                                        vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.gmm_loglik_backward.restype = ctypes.c_int
+    lib.gmm_profile_enable.argtypes = [ctypes.c_int]
+    lib.gmm_profile_enable.restype = ctypes.c_int
+    lib.gmm_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64)]
+    lib.gmm_profile_read.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != GMM_OK:
+        lib = load()
+        detail = lib.gmm_last_error().decode() or lib.gmm_status_string(status).decode()
+        raise GmmError(status, detail)
+
+
+def profile_enable(on: bool) -> None:
+    check(load().gmm_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """(summed E+M tile-kernel time in ms, launch count) since the last read."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    check(load().gmm_profile_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,278 @@
+"""GPU parity of gmm_fit (through the C ABI) against the FP64 oracle.
+
+Tolerances (relative, as the fit's acceptance bar states them):
+  * one E+M step from identical float32 parameters: 1e-5 per parameter
+    array, ||A_gpu - A_ref||_F / ||A_ref||_F;
+  * log-likelihood after a fixed number of iterations: 1e-4, with the
+    floor |dL| <= 1e-4 * max(|L|, N).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2307_00071_amd as gmm
+from paper_2307_00071_amd import _lib, synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) /
+                 max(np.linalg.norm(b), 1e-300))
+
+
+def _to(x, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(DEV, dtype)
+
+
+def _fit(X, K, iters, reg=1e-3, labels=None, theta0=None, mode="shifted"):
+    th = None if theta0 is None else tuple(_to(a) for a in theta0)
+    lab = None if labels is None else _to(labels, torch.int32)
+    r = gmm.fit(_to(X), K, iters=iters, reg_covar=reg, labels=lab, theta0=th,
+                moment_mode=mode)
+    torch.cuda.synchronize()
+    return (r.weights.cpu().numpy().astype(np.float64),
+            r.means.cpu().numpy().astype(np.float64),
+            r.covariances.cpu().numpy().astype(np.float64),
+            r.loglik.cpu().numpy())
+
+
+def _theta32(w, mu, cov):
+    """Round parameters to float32 (what the GPU receives)."""
+    return (w.astype(np.float32).astype(np.float64),
+            mu.astype(np.float32).astype(np.float64),
+            cov.astype(np.float32).astype(np.float64))
+
+
+def _case(name):
+    print("case:", name, flush=True)
+
+
+def _blob_case(seed=0, n_per=1250, k=8):
+    X, _, _ = synth.gaussian_blobs(seed, n_per=n_per, k=k)
+    return X
+
+
+def _depth_subset(n, seed=0):
+    X = synth.depth_frame(seed)
+    rng = np.random.default_rng(seed + 77)
+    idx = np.sort(rng.choice(X.shape[0], n, replace=False))
+    return np.ascontiguousarray(X[idx])
+
+
+# ------------------------------------------------------------ label M-step
+
+@pytest.mark.parametrize("K,n", [(8, 10000), (100, 20037), (1, 777), (200, 9001)])
+def test_label_mstep_parity(K, n):
+    _case("label mstep K=%d n=%d" % (K, n))
+    X = _blob_case() if n == 10000 else _depth_subset(n)
+    lab = synth.kmeanspp_labels(X, K, 1)
+    w, mu, cov, L = _fit(X, K, 0, labels=lab)
+    wr, mur, covr = oracle.mstep_labels(X, lab, K, 1e-3)
+    assert _rel(w, wr) <= 1e-5
+    assert _rel(mu, mur) <= 1e-5
+    assert _rel(cov, covr) <= 1e-5
+    Lr, _, _ = oracle.estep(X, wr, mur, covr)
+    assert abs(L[0] - Lr) <= 1e-5 * max(abs(Lr), n)
+
+
+# ------------------------------------------------------- one E+M step
+
+def _one_step(X, K, theta, reg=1e-3, mode="shifted"):
+    th = _theta32(*theta)
+    w, mu, cov, L = _fit(X, K, 1, reg=reg, theta0=th, mode=mode)
+    wr, mur, covr, L0 = oracle.em_step(X, *th, reg)
+    N = X.shape[0]
+    errs = dict(w=_rel(w, wr), mu=_rel(mu, mur), cov=_rel(cov, covr),
+                L0=abs(L[0] - L0) / max(abs(L0), N))
+    return errs
+
+
+@pytest.mark.parametrize("mode", ["shifted", "two_pass"])
+def test_one_step_blobs(mode):
+    _case("one step blobs " + mode)
+    X = _blob_case()
+    lab = synth.kmeanspp_labels(X, 8, 1)
+    theta = oracle.fit(X, 8, 1e-3, 2, labels=lab)[:3]
+    errs = _one_step(X, 8, theta, mode=mode)
+    print(errs)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+@pytest.mark.parametrize("K,n,mode", [(100, 30011, "shifted"),
+                                      (100, 30011, "two_pass"),
+                                      (16, 4099, "shifted"),
+                                      (200, 25000, "shifted"),
+                                      (1, 1000, "shifted")])
+def test_one_step_depth(K, n, mode):
+    _case("one step depth K=%d n=%d %s" % (K, n, mode))
+    X = _depth_subset(n, seed=K)
+    lab = synth.kmeanspp_labels(X, K, 2)
+    theta = oracle.fit(X, K, 1e-3, 3, labels=lab)[:3]
+    errs = _one_step(X, K, theta, mode=mode)
+    print(errs)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_one_step_from_random_theta():
+    _case("one step random theta")
+    X = _blob_case(3)
+    w, mu, cov = synth.random_theta(12, 5, spread=3.0, smin=0.3, smax=2.0)
+    mu += 5.0
+    errs = _one_step(X, 12, (w, mu, cov), reg=2e-3)
+    print(errs)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+# ----------------------------------------------------- full fits: final L
+
+def test_fit_config_blobs_final_loglik():
+    _case("blobs N=10000 K=8 T=50")
+    X = _blob_case()
+    lab = synth.kmeanspp_labels(X, 8, 1)
+    w, mu, cov, L = _fit(X, 8, 50, labels=lab)
+    wr, mur, covr, Lr = oracle.fit(X, 8, 1e-3, 50, labels=lab)
+    N = X.shape[0]
+    err = np.abs(L - Lr) / np.maximum(np.abs(Lr), N)
+    print("max per-iteration L err", err.max())
+    assert err[-1] <= 1e-4
+    assert err.max() <= 1e-4
+    assert _rel(mu, mur) <= 1e-4
+
+
+def test_fit_depth_frame_full_size_final_loglik():
+    """The benchmark workload: N = 307,200, K = 100, T = 100."""
+    _case("depth frame N=307200 K=100 T=100")
+    X = synth.depth_frame(0)
+    lab = synth.kmeanspp_labels(X, 100, 1)
+    w, mu, cov, L = _fit(X, 100, 100, labels=lab)
+    wr, mur, covr, Lr = oracle.fit(X, 100, 1e-3, 100, labels=lab)
+    N = X.shape[0]
+    err = np.abs(L - Lr) / np.maximum(np.abs(Lr), N)
+    print("L gpu %.6f oracle %.6f, max per-iteration err %.3e"
+          % (L[-1], Lr[-1], err.max()))
+    assert err[-1] <= 1e-4
+    assert np.all(np.isfinite(L))
+
+
+def test_monotone_with_zero_reg():
+    _case("monotone lambda=0")
+    X = _blob_case(6)
+    lab = synth.kmeanspp_labels(X, 8, 1)
+    _, _, _, L = _fit(X, 8, 30, reg=0.0, labels=lab)
+    # FP32 E-step: allow rounding-level wobble at the plateau
+    assert np.all(np.diff(L) >= -1e-6 * abs(L[-1]))
+
+
+# ------------------------------------------------------------ properties
+
+def test_deterministic_bitwise():
+    _case("determinism")
+    X = _depth_subset(50000)
+    lab = synth.kmeanspp_labels(X, 64, 3)
+    a = _fit(X, 64, 10, labels=lab)
+    b = _fit(X, 64, 10, labels=lab)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_outputs_valid_mixture():
+    _case("valid mixture")
+    X = _depth_subset(40000, seed=4)
+    lab = synth.kmeanspp_labels(X, 50, 4)
+    w, mu, cov, L = _fit(X, 50, 20, reg=1e-3, labels=lab)
+    assert abs(w.sum() - 1.0) <= 1e-5
+    for b in range(50):
+        np.testing.assert_array_equal(cov[b], cov[b].T)
+        assert np.linalg.eigvalsh(cov[b]).min() >= 1e-3 * (1 - 1e-4)
+
+
+def test_warm_restart_matches_continuous_fit():
+    """theta out of fit(T1) fed back as theta0 continues the same fit (up to
+    the float32 rounding of the handed-over parameters)."""
+    _case("warm restart")
+    X = _blob_case(2)
+    lab = synth.kmeanspp_labels(X, 8, 1)
+    w1, mu1, cov1, L1 = _fit(X, 8, 10, labels=lab)
+    w2, mu2, cov2, L2 = _fit(X, 8, 10, theta0=(w1, mu1, cov1))
+    w3, mu3, cov3, L3 = _fit(X, 8, 20, labels=lab)
+    assert abs(L2[0] - L1[-1]) <= 1e-6 * abs(L1[-1])
+    assert abs(L2[-1] - L3[-1]) <= 1e-5 * abs(L3[-1])
+
+
+# ------------------------------------------------------------ edge cases
+
+@pytest.mark.parametrize("n,K", [(1, 1), (5, 2), (63, 3), (64, 4), (65, 5),
+                                 (128, 128), (129, 7)])
+def test_small_and_ragged_sizes(n, K):
+    _case("ragged n=%d K=%d" % (n, K))
+    rng = np.random.default_rng(n)
+    X = rng.normal(size=(n, 3)).astype(np.float32) + 3.0
+    lab = (np.arange(n) % K).astype(np.int32)
+    w, mu, cov, L = _fit(X, K, 3, labels=lab)
+    wr, mur, covr, Lr = oracle.fit(X, K, 1e-3, 3, labels=lab)
+    assert np.abs(L - Lr).max() / max(np.abs(Lr).max(), n) <= 1e-5
+    assert _rel(mu, mur) <= 1e-5
+    assert _rel(cov, covr) <= 1e-5
+
+
+def test_max_k():
+    _case("K = GMM_MAX_K")
+    X = _depth_subset(20000, seed=9)
+    K = _lib.GMM_MAX_K
+    lab = synth.kmeanspp_labels(X, K, 1)
+    w, mu, cov, L = _fit(X, K, 1, labels=lab)
+    wr, mur, covr, Lr = oracle.fit(X, K, 1e-3, 1, labels=lab)
+    assert np.abs(L - Lr).max() / max(np.abs(Lr).max(), X.shape[0]) <= 1e-5
+    assert _rel(mu, mur) <= 1e-5
+
+
+def test_invalid_arguments_raise():
+    _case("invalid args")
+    X = _to(np.zeros((10, 3), np.float32))
+    lab = _to(np.zeros(10, np.int32), torch.int32)
+    with pytest.raises(_lib.GmmError):
+        gmm.fit(X, 11, iters=1, labels=_to(np.zeros(10), torch.int32))
+    with pytest.raises(_lib.GmmError):
+        gmm.fit(X, _lib.GMM_MAX_K + 1, iters=1, labels=lab)
+    with pytest.raises(_lib.GmmError):
+        gmm.fit(X, 2, iters=1, reg_covar=-1.0, labels=lab)
+
+
+def test_device_errors_reported():
+    _case("device errors")
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(100, 3)).astype(np.float32)
+    bad = X.copy()
+    bad[17, 1] = np.nan
+    with pytest.raises(_lib.GmmError) as e:
+        _fit(bad, 2, 2, labels=np.arange(100) % 2)
+    assert e.value.status == 3
+    with pytest.raises(_lib.GmmError) as e:
+        _fit(X, 2, 2, labels=(np.arange(100) % 3))
+    assert e.value.status == 1
+    w = np.array([0.5, 0.5])
+    mu = np.zeros((2, 3))
+    cov = np.stack([np.eye(3), -np.eye(3)])
+    with pytest.raises(_lib.GmmError) as e:
+        _fit(X, 2, 1, theta0=(w, mu, cov))
+    assert e.value.status == 2
+
+
+def test_loglik_matches_oracle_with_pose():
+    _case("loglik with pose")
+    X = _depth_subset(30000, seed=5)
+    lab = synth.kmeanspp_labels(X, 60, 5)
+    w, mu, cov, _ = oracle.fit(X, 60, 1e-3, 5, labels=lab)
+    th = _theta32(w, mu, cov)
+    pose = synth.random_pose(2).astype(np.float32).astype(np.float64)
+    L, lse = gmm.loglik(_to(X), *(_to(a) for a in th), pose6=_to(pose),
+                        return_lse=True)
+    Lr, lser = oracle.loglik_pose(X, pose, *th, want_lse=True)
+    assert abs(L.item() - Lr) <= 1e-5 * max(abs(Lr), X.shape[0])
+    np.testing.assert_allclose(lse.cpu().numpy(), lser, rtol=1e-4, atol=2e-4)
+    L0 = gmm.loglik(_to(X), *(_to(a) for a in th))
+    Lr0 = oracle.loglik_pose(X, None, *th)
+    assert abs(L0.item() - Lr0) <= 1e-5 * max(abs(Lr0), X.shape[0])
