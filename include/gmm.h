@@ -124,8 +124,7 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
  *           R = exp([omega]_x) (axis-angle), or NULL for the identity.
  *  w        used as given (no renormalisation); must be > 0.
  *  out_L    device float64 scalar.
- *  out_lse  device float32 N (per-point ln sum_b pi_b N(y_n|.)), or NULL;
- *           pass it to gmm_loglik_backward to skip one E-step.
+ *  out_lse  device float32 N (per-point ln sum_b pi_b N(y_n|.)), or NULL.
  *  Does not synchronise.  Errors: host-side as gmm_fit; device-side
  *  NOT_SPD / NONFINITE via gmm_workspace_status(). */
 size_t gmm_loglik_workspace_size(int64_t n, int32_t k);
@@ -136,8 +135,8 @@ gmm_status gmm_loglik(const float *pts, int64_t n, const float *pose6,
                       void *ws, size_t ws_bytes, void *stream);
 
 /* gmm_loglik_backward: gradient of grad_L * L (the inputs as gmm_loglik).
- *  lse      device float32 N from gmm_loglik on the same inputs, or NULL
- *           (then it is recomputed).
+ *  One pass over the points re-forms the responsibilities (the per-point
+ *  normaliser comes with them, so no forward state is needed).
  *  grad_L   device float64 scalar (the upstream gradient), or NULL for 1.
  *  Outputs (device float32, any may be NULL):
  *   g_pose6  6: (dL/domega, dL/dt), omega through the SO(3) left Jacobian;
@@ -151,11 +150,10 @@ size_t gmm_loglik_backward_workspace_size(int64_t n, int32_t k);
 
 gmm_status gmm_loglik_backward(const float *pts, int64_t n, const float *pose6,
                                int32_t k, const float *w, const float *mu,
-                               const float *cov, const float *lse,
-                               const double *grad_L, float *g_pose6,
-                               float *g_pts, float *g_w, float *g_mu,
-                               float *g_cov, void *ws, size_t ws_bytes,
-                               void *stream);
+                               const float *cov, const double *grad_L,
+                               float *g_pose6, float *g_pts, float *g_w,
+                               float *g_mu, float *g_cov, void *ws,
+                               size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------ profiling
  * Kernel timing for benchmarks.  While enabled (per calling host thread),

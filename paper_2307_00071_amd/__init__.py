@@ -144,9 +144,11 @@ def loglik(points, w, mu, cov, pose6=None, return_lse=False):
     return (out, lse) if return_lse else out
 
 
-def loglik_backward(points, w, mu, cov, pose6=None, lse=None, grad_L=None,
+def loglik_backward(points, w, mu, cov, pose6=None, grad_L=None,
                     need=("pose", "pts", "w", "mu", "cov")):
-    """Gradient of grad_L * L; returns a dict of float32 tensors."""
+    """Gradient of grad_L * L with respect to pose (omega, t), points,
+    weights, means and covariances; returns a dict of float32 tensors
+    (None for keys not in ``need``)."""
     torch = _torch()
     lib = _lib.load()
     pts = _check_points(points)
@@ -154,18 +156,21 @@ def loglik_backward(points, w, mu, cov, pose6=None, lse=None, grad_L=None,
     n = pts.shape[0]
     w, mu, cov, k = _gmm_args(w, mu, cov, dev)
     pose = None if pose6 is None else pose6.to(device=dev, dtype=torch.float32).contiguous()
-    g = {}
     shapes = dict(pose=(6,), pts=(n, 3), w=(k,), mu=(k, 3), cov=(k, 3, 3))
-    for key in shapes:
-        g[key] = torch.empty(shapes[key], dtype=torch.float32, device=dev) \
-            if key in need else None
+    g = {key: (torch.empty(shapes[key], dtype=torch.float32, device=dev)
+               if key in need else None) for key in shapes}
+    if pose is None:
+        g["pose"] = None
     gl = None if grad_L is None else grad_L.to(device=dev, dtype=torch.float64).contiguous()
-    lse_t = None if lse is None else lse.to(device=dev, dtype=torch.float32).contiguous()
     nb = lib.gmm_loglik_backward_workspace_size(n, k)
-    ws = _workspace(max(nb, 256), dev)
+    if nb == 0:
+        _lib.check(lib.gmm_loglik_backward(None, n, None, k, None, None, None,
+                                           None, None, None, None, None, None,
+                                           None, 0, None))
+    ws = _workspace(nb, dev)
     _lib.check(lib.gmm_loglik_backward(
-        _ptr(pts), n, _ptr(pose), k, _ptr(w), _ptr(mu), _ptr(cov), _ptr(lse_t),
-        _ptr(gl), _ptr(g["pose"]), _ptr(g["pts"]), _ptr(g["w"]), _ptr(g["mu"]),
+        _ptr(pts), n, _ptr(pose), k, _ptr(w), _ptr(mu), _ptr(cov), _ptr(gl),
+        _ptr(g["pose"]), _ptr(g["pts"]), _ptr(g["w"]), _ptr(g["mu"]),
         _ptr(g["cov"]), _ptr(ws), ws.numel(), _stream(dev)))
     return g
 
@@ -178,18 +183,18 @@ def _make_autograd():
 
         @staticmethod
         def forward(ctx, points, pose6, w, mu, cov):
-            out, lse = loglik(points, w, mu, cov, pose6=pose6, return_lse=True)
-            ctx.save_for_backward(points, pose6, w, mu, cov, lse)
+            out = loglik(points, w, mu, cov, pose6=pose6)
+            ctx.save_for_backward(points, pose6, w, mu, cov)
             return out
 
         @staticmethod
         def backward(ctx, grad_out):
-            points, pose6, w, mu, cov, lse = ctx.saved_tensors
+            points, pose6, w, mu, cov = ctx.saved_tensors
             need = []
             for key, i in (("pts", 0), ("pose", 1), ("w", 2), ("mu", 3), ("cov", 4)):
                 if ctx.needs_input_grad[i]:
                     need.append(key)
-            g = loglik_backward(points, w, mu, cov, pose6=pose6, lse=lse,
+            g = loglik_backward(points, w, mu, cov, pose6=pose6,
                                 grad_L=grad_out, need=tuple(need))
             return g["pts"], g["pose"], g["w"], g["mu"], g["cov"]
 

@@ -70,7 +70,7 @@ def load():
     lib.gmm_loglik_backward_workspace_size.argtypes = [i64, i32]
     lib.gmm_loglik_backward_workspace_size.restype = sz
     lib.gmm_loglik_backward.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp, vp,
-                                        vp, vp, vp, vp, vp, vp, sz, vp]
+                                        vp, vp, vp, vp, vp, sz, vp]
     lib.gmm_loglik_backward.restype = ctypes.c_int
     lib.gmm_profile_enable.argtypes = [ctypes.c_int]
     lib.gmm_profile_enable.restype = ctypes.c_int

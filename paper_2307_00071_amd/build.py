@@ -7,6 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "gmm.hip")
+CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmm.so")
 ARCH = "gfx950"
 
@@ -26,7 +27,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False, extra=None) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
+    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            *(extra or []), "-o", tmp, SRC]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -1,0 +1,975 @@
+// Device code of the MI355X (gfx950) GMM EM library: helpers and kernels.
+// Included once, by gmm.hip.
+//
+// One EM iteration is three launches:
+//   tile loop  - persistent tiles of T points.  E-phase: lanes = points,
+//                components wave-uniform (scalar loads of the parameter
+//                block), e_pb = 2^(log2(e) (l_pb - C)) into LDS and the
+//                per-point normaliser (eq. 1-3).  M-phase: lanes =
+//                (component, point subset); each lane reads gamma_pb from LDS
+//                and keeps its own sum g, sum g d, sum g d d^T in registers
+//                (FP32 over a tile, FP64 across tiles): no cross-lane
+//                reduction per point.  One FP64 partial row per block.
+//   reduce_rows_kernel, update_kernel - fixed-order FP64 sum of the rows
+//                (wide, then one block), and the FP64 M-step, the FP64 3x3
+//                Cholesky and the eq. 3 terms for the next iteration.
+// Every reduction has a fixed order, so a fit is bitwise reproducible for a
+// given launch configuration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "gmm.h"
+
+namespace gmm_dev {
+
+// ------------------------------------------------------------------ constants
+
+constexpr double kLog2e = 1.44269504088896340736;
+constexpr double kLn2 = 0.693147180559945309417;
+constexpr double kLn2Pi = 1.83787706640934548356;
+constexpr double kEpsN = 10.0 * 2.220446049250313080847e-16;  // N_b guard
+constexpr int kParStride = 16;   // floats per component in the E-step block
+constexpr int kTh64Stride = 16;  // doubles per component in the FP64 state
+constexpr int kNStat = 10;       // N, S1 (3), S2 lower triangle (6)
+
+// status bits (device status word)
+constexpr uint32_t kStBadArg = 1u << GMM_ERR_INVALID_ARG;
+constexpr uint32_t kStNotSpd = 1u << GMM_ERR_NOT_SPD;
+constexpr uint32_t kStNonFinite = 1u << GMM_ERR_NONFINITE;
+
+enum TileMode { kSoftStats = 0, kSoftLogLik = 1, kLabels = 2 };
+// kUpdNone: only the log-likelihood (and optional FP32 outputs);
+// kUpdMeanOnly: the new means become the next pass's shift, the E-step
+// block is carried over unchanged; kUpdFull: the complete M-step.
+enum UpdMode { kUpdFull = 0, kUpdMeanOnly = 1, kUpdNone = 2 };
+
+// ------------------------------------------------------------------ layout
+// E-step parameter block ("cpar"), per component (16 floats):
+//   [0..2] mu  [3] (c_b - C) * log2(e)  [4..9] s * P (P00 P10 P11 P20 P21 P22)
+// with s = sqrt(log2(e) / 2), c_b = ln pi_b - 3/2 ln 2pi + sum_j ln P_jj
+// (eq. 3) and C = max_b c_b, so [3] - |P' (x - mu)|^2 = log2(e)(l_nb - C) <= 0.
+// After the K blocks: C * log2(e) as a double.
+// Shift array: the FP32 point the M-phase subtracts, per component.
+// FP64 state ("th64"), per component (16 doubles):
+//   [0] pi  [1..3] mu  [4..9] Sigma lower (00 10 11 20 21 22)  [10] N_b
+
+// ------------------------------------------------------- device helpers
+
+__device__ inline void set_status(uint32_t *st, uint32_t bits) {
+  atomicOr(st, bits);
+}
+
+// Cholesky of the 3x3 SPD matrix with lower triangle C = (00 10 11 20 21 22).
+// Returns false on a non-positive or non-finite pivot.
+__device__ inline bool chol3(const double *C, double *L) {
+  double a = C[0];
+  if (!(a > 0.0) || !isfinite(a)) return false;
+  double l00 = sqrt(a);
+  double l10 = C[1] / l00;
+  double b = C[2] - l10 * l10;
+  if (!(b > 0.0) || !isfinite(b)) return false;
+  double l11 = sqrt(b);
+  double l20 = C[3] / l00;
+  double l21 = (C[4] - l20 * l10) / l11;
+  double c = C[5] - l20 * l20 - l21 * l21;
+  if (!(c > 0.0) || !isfinite(c)) return false;
+  double l22 = sqrt(c);
+  L[0] = l00; L[1] = l10; L[2] = l11; L[3] = l20; L[4] = l21; L[5] = l22;
+  return true;
+}
+
+// P = L^-1 (lower) by forward substitution, same packed order.
+__device__ inline void tri_inv3(const double *L, double *P) {
+  double p00 = 1.0 / L[0], p11 = 1.0 / L[2], p22 = 1.0 / L[5];
+  double p10 = -L[1] * p00 / L[2];
+  double p21 = -L[4] * p11 / L[5];
+  double p20 = -(L[3] * p00 + L[4] * p10) / L[5];
+  P[0] = p00; P[1] = p10; P[2] = p11; P[3] = p20; P[4] = p21; P[5] = p22;
+}
+
+// Stores one component (pi, mu, Sigma) in the FP64 state, its E-step block
+// (all but [3]) and its shift; returns c_b * log2(e), or -inf when Sigma is
+// not SPD (the component then contributes 2^-inf = 0 everywhere).
+__device__ inline double component_terms(int b, double pi, const double *mu,
+                                         const double *C, double Nb,
+                                         float *cpar, float4 *shift,
+                                         double *th64) {
+  double *t = th64 + (size_t)b * kTh64Stride;
+  t[0] = pi;
+  for (int j = 0; j < 3; ++j) t[1 + j] = mu[j];
+  for (int j = 0; j < 6; ++j) t[4 + j] = C[j];
+  t[10] = Nb;
+  const float mf0 = (float)mu[0], mf1 = (float)mu[1], mf2 = (float)mu[2];
+  shift[b] = make_float4(mf0, mf1, mf2, 0.0f);
+  float *q = cpar + (size_t)b * kParStride;
+  q[0] = mf0; q[1] = mf1; q[2] = mf2;
+  double L[6], P[6];
+  if (!chol3(C, L)) {
+    for (int j = 0; j < 6; ++j) q[4 + j] = 0.0f;
+    return -INFINITY;
+  }
+  tri_inv3(L, P);
+  const double logdiag = log(P[0]) + log(P[2]) + log(P[5]);
+  const double c = log(pi) - 1.5 * kLn2Pi + logdiag;
+  const double s = sqrt(0.5 * kLog2e);
+  for (int j = 0; j < 6; ++j) q[4 + j] = (float)(s * P[j]);
+  return c * kLog2e;
+}
+
+// Block-wide (NT threads) fixed-order tree reductions over NT doubles.
+template <int NT>
+__device__ inline double block_sum(double v, double *scratch) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  scratch[tid] = v;
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if (tid < h) scratch[tid] += scratch[tid + h];
+    __syncthreads();
+  }
+  return scratch[0];
+}
+
+template <int NT>
+__device__ inline double block_max(double v, double *scratch) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  scratch[tid] = v;
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if (tid < h) scratch[tid] = fmax(scratch[tid], scratch[tid + h]);
+    __syncthreads();
+  }
+  return scratch[0];
+}
+
+// With sC[b] = c_b * log2(e) for every component: C = max_b c_b, each
+// component's [3] = c_b - C and the header C.
+template <int NT>
+__device__ inline void apply_bound(int K, const double *sC, float *cpar,
+                                   double *scratch) {
+  double m = -INFINITY;
+  for (int b = threadIdx.x; b < K; b += NT) m = fmax(m, sC[b]);
+  double C = block_max<NT>(m, scratch);
+  if (!isfinite(C)) C = 0.0;
+  for (int b = threadIdx.x; b < K; b += NT) {
+    const double c = sC[b];
+    cpar[(size_t)b * kParStride + 3] = isfinite(c) ? (float)(c - C) : -INFINITY;
+  }
+  if (threadIdx.x == 0) *reinterpret_cast<double *>(cpar + (size_t)K * kParStride) = C;
+}
+
+// ------------------------------------------------------------------ M-step
+// From the reduced statistics tot[] (column s*K + b: N0, S1 (3), S2 (6); the
+// log-likelihood at 10 K) and the shift m the tile kernel subtracted:
+//   N_b = N0 + eps,  mu = (S1 + N0 m) / N_b,  delta = mu - m,
+//   Sigma = (S2 - S1 delta^T - delta S1^T + N0 delta delta^T) / N_b + lambda I
+// which is sum g (x - mu)(x - mu)^T / N_b + lambda I exactly;
+//   pi_b = N_b / sum_a N_a, then the eq. 3 terms for the next E-step.
+// Runs in one block of NT threads; sN, sC are K-double LDS arrays.
+template <int NT>
+__device__ void em_update_block(const double *tot, int K, int umode, double reg,
+                                const float *cpar_in, const float4 *shift_in,
+                                float *cpar_out, float4 *shift_out,
+                                double *th64, double *sN, double *sC,
+                                double *scratch, uint32_t *status) {
+  const int tid = threadIdx.x;
+  if (umode == kUpdMeanOnly) {
+    for (int b = tid; b < K; b += NT) {
+      const double N0 = tot[b];
+      const float4 mf = shift_in[b];
+      const double Nb = N0 + kEpsN;
+      const double m[3] = {mf.x, mf.y, mf.z};
+      float mu[3];
+      bool fin = isfinite(N0);
+      for (int j = 0; j < 3; ++j) {
+        const double S1 = tot[(1 + j) * K + b];
+        fin = fin && isfinite(S1);
+        mu[j] = (float)((S1 + N0 * m[j]) / Nb);
+      }
+      if (!fin) set_status(status, kStNonFinite);
+      shift_out[b] = make_float4(mu[0], mu[1], mu[2], 0.0f);
+    }
+    // the E-step block of the current parameters carries over
+    const int nf = (K + 1) * kParStride;
+    for (int i = tid; i < nf; i += NT) cpar_out[i] = cpar_in[i];
+    return;
+  }
+  // umode == kUpdFull
+  const int ij[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
+  double part = 0.0;
+  for (int b = tid; b < K; b += NT) {
+    const double N0 = tot[b];
+    const double S1[3] = {tot[1 * K + b], tot[2 * K + b], tot[3 * K + b]};
+    const float4 mf = shift_in[b];
+    const double m[3] = {mf.x, mf.y, mf.z};
+    const double Nb = N0 + kEpsN;
+    double mu[3], dl[3];
+    for (int j = 0; j < 3; ++j) {
+      mu[j] = (S1[j] + N0 * m[j]) / Nb;
+      dl[j] = mu[j] - m[j];
+    }
+    bool fin = isfinite(N0) && isfinite(S1[0]) && isfinite(S1[1]) && isfinite(S1[2]);
+    double *t = th64 + (size_t)b * kTh64Stride;
+    for (int j = 0; j < 6; ++j) {
+      const int r = ij[j][0], c = ij[j][1];
+      const double s2 = tot[(4 + j) * K + b];
+      const double v = s2 - S1[r] * dl[c] - dl[r] * S1[c] + N0 * dl[r] * dl[c];
+      t[4 + j] = v / Nb + ((r == c) ? reg : 0.0);
+      fin = fin && isfinite(s2);
+    }
+    if (!fin) set_status(status, kStNonFinite);
+    for (int j = 0; j < 3; ++j) t[1 + j] = mu[j];
+    sN[b] = Nb;
+    part += Nb;
+  }
+  // sum_a N_a in a fixed order: per-thread partials (fixed component
+  // stride) then the fixed tree
+  const double Ntot = block_sum<NT>(part, scratch);
+  for (int b = tid; b < K; b += NT) {
+    const double *t = th64 + (size_t)b * kTh64Stride;
+    const double mu[3] = {t[1], t[2], t[3]};
+    const double C[6] = {t[4], t[5], t[6], t[7], t[8], t[9]};
+    const double c = component_terms(b, sN[b] / Ntot, mu, C, sN[b], cpar_out,
+                                     shift_out, th64);
+    if (!isfinite(c)) set_status(status, kStNotSpd);
+    sC[b] = c;
+  }
+  apply_bound<NT>(K, sC, cpar_out, scratch);
+}
+
+// Caller-supplied theta_0 (FP32 w, mu, cov) -> FP64 state and E-step block;
+// weights used as given.  One block of kPreThreads threads.
+constexpr int kPreThreads = 1024;
+__global__ __launch_bounds__(kPreThreads) void precompute_kernel(
+    const float *__restrict__ w, const float *__restrict__ mu,
+    const float *__restrict__ cov, int K, float *cpar, float4 *shift,
+    double *th64, uint32_t *status) {
+  __shared__ double scratch[kPreThreads];
+  __shared__ double sC[GMM_MAX_K];
+  for (int b = threadIdx.x; b < K; b += kPreThreads) {
+    double pi = w[b];
+    double m[3] = {mu[3 * b], mu[3 * b + 1], mu[3 * b + 2]};
+    const float *c = cov + 9 * b;
+    double C[6] = {c[0], c[3], c[4], c[6], c[7], c[8]};
+    if (!(pi > 0.0) || !isfinite(pi) || !isfinite(m[0]) || !isfinite(m[1]) ||
+        !isfinite(m[2])) {
+      set_status(status, kStBadArg);
+      pi = 1.0;
+    }
+    const double cc = component_terms(b, pi, m, C, 0.0, cpar, shift, th64);
+    if (!isfinite(cc)) set_status(status, kStNotSpd);
+    sC[b] = cc;
+  }
+  apply_bound<kPreThreads>(K, sC, cpar, scratch);
+}
+
+// ------------------------------------------------------------ stage kernel
+// AoS N x 3 (caller) -> float4 (x, y, z, tag) padded to a tile multiple.
+// tag (int bits) = label in label mode, 0 for a real point otherwise, and -1
+// for padding.  With a pose, y = R x + t in FP32.
+__global__ void stage_kernel(const float *__restrict__ pts, int64_t n,
+                             int64_t npad, const int32_t *__restrict__ labels,
+                             int K, const float *__restrict__ Rt,
+                             float4 *__restrict__ out, uint32_t *status) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  if (i >= n) {
+    out[i] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+    return;
+  }
+  float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+    set_status(status, kStNonFinite);
+    x = y = z = 0.0f;
+  }
+  if (Rt) {
+    float u = fmaf(Rt[0], x, fmaf(Rt[1], y, fmaf(Rt[2], z, Rt[9])));
+    float v = fmaf(Rt[3], x, fmaf(Rt[4], y, fmaf(Rt[5], z, Rt[10])));
+    float w = fmaf(Rt[6], x, fmaf(Rt[7], y, fmaf(Rt[8], z, Rt[11])));
+    x = u; y = v; z = w;
+  }
+  int tag = 0;
+  if (labels) {
+    tag = labels[i];
+    if (tag < 0 || tag >= K) {
+      set_status(status, kStBadArg);
+      tag = -1;
+    }
+  }
+  out[i] = make_float4(x, y, z, __int_as_float(tag));
+}
+
+// --------------------------------------------------------------- pose kernel
+// R = exp([omega]_x) (Rodrigues), the SO(3) left Jacobian J, both FP64, and
+// an FP32 copy (R row-major, t) for the staging kernel.
+// pose64: [0..8] R, [9..11] t, [12..20] J.
+__global__ void pose_kernel(const float *__restrict__ pose6, double *pose64,
+                            float *Rt32) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double w[3] = {pose6[0], pose6[1], pose6[2]};
+  double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  double th = sqrt(th2), a, bb, e;
+  if (th < 1e-4) {
+    a = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+    bb = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    e = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+  } else {
+    a = sin(th) / th;
+    bb = (1.0 - cos(th)) / th2;
+    e = (th - sin(th)) / (th2 * th);
+  }
+  double S[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+  double S2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += S[i * 3 + k] * S[k * 3 + j];
+      S2[i * 3 + j] = s;
+    }
+  for (int i = 0; i < 9; ++i) {
+    double id = (i % 4 == 0) ? 1.0 : 0.0;
+    pose64[i] = id + a * S[i] + bb * S2[i];        // R
+    pose64[12 + i] = id + bb * S[i] + e * S2[i];   // J_l
+    Rt32[i] = (float)pose64[i];
+  }
+  for (int j = 0; j < 3; ++j) {
+    pose64[9 + j] = pose6[3 + j];
+    Rt32[9 + j] = pose6[3 + j];
+  }
+}
+
+// Clears the status word and the ticket counters and, for a label start,
+// the shift array (the first label pass accumulates about the origin).
+__global__ void init_kernel(uint32_t *status, unsigned *counters, int ncnt,
+                            float4 *shift, int K) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  if (i == 0) *status = 0u;
+  for (int j = i; j < ncnt; j += stride) counters[j] = 0u;
+  if (shift)
+    for (int b = i; b < K; b += stride) shift[b] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// ------------------------------------------------------------ tile kernel
+//
+// Per tile of T points (T = one wave of points):
+//  E-phase, lanes = (point p, component group g): each lane walks its
+//  group's components (wave-uniform, scalar loads) and forms
+//    l'_pb = log2(e) (l_pb - C),  C = max_a c_a  (so l'_pb <= 0),
+//  e_pb = 2^l'_pb.  The per-point sum s_p = sum_b e_pb then gives
+//  lse_p = ln 2 (C' + log2 s_p) and gamma_pb = e_pb / s_p.  When s_p falls
+//  below 2^-100 (a point far from every component) the point is redone
+//  exactly with its own maximum, so nothing underflows.
+//  M-phase, lanes = (component b, point subset q): a lane reads gamma_pb for
+//  its TRIP consecutive points from LDS and accumulates
+//    N += g, S1 += g d, S2 += g d d^T,  d = x_p - m_b  (FP32 over the tile,
+//  then FP64), m_b the shift array.
+// With NCH > 1 (large K) the LDS holds one chunk of components at a time:
+// the E-phase first forms s_p only, then each chunk recomputes its e_pb.
+
+template <int BLOCK, int T>
+struct TileShape {
+  static constexpr int G = BLOCK / T;  // component groups in the E-phase
+  static constexpr int TS = T + 1;     // LDS row: T points + 1 zero pad (odd)
+  static_assert(BLOCK % T == 0, "tile must divide the block");
+  static_assert(T % 64 == 0, "a wave must hold one component group");
+};
+
+// LDS: [E (also the end-of-kernel subset sums)][Xs][reds][Mp][wL]
+template <int BLOCK, int T>
+__host__ __device__ constexpr size_t tile_lds_bytes_e(int K, int KC) {
+  size_t e = (size_t)KC * TileShape<BLOCK, T>::TS * sizeof(float);
+  (void)K;
+  size_t d = (size_t)BLOCK * sizeof(double);
+  size_t m = e > d ? e : d;
+  return (m + 15) & ~(size_t)15;
+}
+
+template <int BLOCK, int T>
+__host__ __device__ constexpr size_t tile_lds_bytes(int K, int KC) {
+  using S = TileShape<BLOCK, T>;
+  return tile_lds_bytes_e<BLOCK, T>(K, KC) + S::TS * sizeof(float4) +
+         (size_t)S::G * T * sizeof(float) + T * sizeof(float) +
+         (BLOCK / 64) * sizeof(double);
+}
+
+// l'_pb of one component (eq. 3 in log2 units, relative to the bound).
+__device__ __forceinline__ float comp_logterm(const float *__restrict__ q,
+                                              float x, float y, float z) {
+  float d0 = x - q[0], d1 = y - q[1], d2 = z - q[2];
+  float z0 = q[4] * d0;
+  float z1 = fmaf(q[5], d0, q[6] * d1);
+  float z2 = fmaf(q[7], d0, fmaf(q[8], d1, q[9] * d2));
+  float l = fmaf(-z0, z0, q[3]);
+  l = fmaf(-z1, z1, l);
+  return fmaf(-z2, z2, l);
+}
+
+// Sufficient statistics of one component over TRIP consecutive points.
+template <int TRIP>
+__device__ __forceinline__ void mstep_run(const float *Eb, const float4 *Xb,
+                                          float4 sh, double *acc) {
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f,
+        a7 = 0.f, a8 = 0.f, a9 = 0.f;
+#pragma unroll
+  for (int j = 0; j < TRIP; ++j) {
+    const float4 xr = Xb[j];
+    const float gm = Eb[j] * xr.w;
+    const float d0 = xr.x - sh.x, d1 = xr.y - sh.y, d2 = xr.z - sh.z;
+    const float w0 = gm * d0, w1 = gm * d1, w2 = gm * d2;
+    a0 += gm;
+    a1 += w0; a2 += w1; a3 += w2;
+    a4 = fmaf(w0, d0, a4);
+    a5 = fmaf(w1, d0, a5);
+    a6 = fmaf(w1, d1, a6);
+    a7 = fmaf(w2, d0, a7);
+    a8 = fmaf(w2, d1, a8);
+    a9 = fmaf(w2, d2, a9);
+  }
+  acc[0] += a0; acc[1] += a1; acc[2] += a2; acc[3] += a3; acc[4] += a4;
+  acc[5] += a5; acc[6] += a6; acc[7] += a7; acc[8] += a8; acc[9] += a9;
+}
+
+// Integer arguments of the tile kernel (pointers are separate __restrict__
+// arguments so the parameter block is read with scalar loads).
+struct TileArgs {
+  int ntiles, K, KC, P, mode, ncols;
+};
+
+template <int BLOCK, int T, int NCH, int TRIP>
+__global__ __launch_bounds__(BLOCK) void em_tile_kernel(
+    const float4 *__restrict__ pts,    // staged (x, y, z, tag), ntiles * T
+    const float *__restrict__ cpar,    // K x 16 floats, then the bound C
+    const float4 *__restrict__ shift,  // K
+    double *__restrict__ part,         // grid rows of ncols
+    float *__restrict__ lse_out,       // N or NULL
+    TileArgs a) {
+  using S = TileShape<BLOCK, T>;
+  constexpr int G = S::G, TS = S::TS;
+  constexpr int trip = TRIP;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int K = a.K, KC = a.KC, P = a.P, mode = a.mode;
+  float *E = reinterpret_cast<float *>(smem);
+  float4 *Xs = reinterpret_cast<float4 *>(smem + tile_lds_bytes_e<BLOCK, T>(K, KC));
+  float *reds = reinterpret_cast<float *>(Xs + TS);
+  float *Mp = reds + G * T;
+  double *wL = reinterpret_cast<double *>(Mp + T);
+
+  const int tid = threadIdx.x;
+  const int p = tid % T;
+  // T is a multiple of the wave size, so g is wave-uniform; readfirstlane
+  // makes that visible to the compiler: the component loops then run on
+  // scalar registers with scalar loads of the parameter block.
+  const int g = __builtin_amdgcn_readfirstlane(tid / T);
+  const int b_lo = (g * K) / G;
+  const int b_hi = ((g + 1) * K) / G;
+  const bool mact = tid < KC * P;
+  const int mb = mact ? tid % KC : 0;
+  const int mq = mact ? tid / KC : 0;
+  const double Cb = *reinterpret_cast<const double *>(cpar + (size_t)K * kParStride);
+
+  float4 sh[NCH];
+  double acc[NCH][kNStat];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int b = c * KC + mb;
+    sh[c] = (b < K) ? shift[b] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < kNStat; ++j) acc[c][j] = 0.0;
+  }
+  double Lacc = 0.0;
+  // the zero pad column of E and pad entry of Xs (read by the last subset)
+  for (int b = tid; b < KC; b += BLOCK) E[b * TS + T] = 0.0f;
+  if (tid < TS - T) Xs[T + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const float4 x = pts[(size_t)tile * T + p];
+    const int tag = __float_as_int(x.w);
+    const bool valid = tag >= 0;
+    if (mode != kLabels) {
+      float s = 0.0f;
+      const float *q = cpar + (size_t)b_lo * kParStride;
+      float *Ep = E + (size_t)b_lo * TS + p;
+      int b = b_lo;
+      if (NCH == 1) {
+        for (; b + 4 <= b_hi; b += 4, q += 4 * kParStride, Ep += 4 * TS) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float e = __builtin_amdgcn_exp2f(
+                comp_logterm(q + u * kParStride, x.x, x.y, x.z));
+            Ep[u * TS] = e;
+            s += e;
+          }
+        }
+        for (; b < b_hi; ++b, q += kParStride, Ep += TS) {
+          const float e = __builtin_amdgcn_exp2f(comp_logterm(q, x.x, x.y, x.z));
+          *Ep = e;
+          s += e;
+        }
+      } else {
+        for (; b + 4 <= b_hi; b += 4, q += 4 * kParStride) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            s += __builtin_amdgcn_exp2f(
+                comp_logterm(q + u * kParStride, x.x, x.y, x.z));
+        }
+        for (; b < b_hi; ++b, q += kParStride)
+          s += __builtin_amdgcn_exp2f(comp_logterm(q, x.x, x.y, x.z));
+      }
+      reds[g * T + p] = s;
+      __syncthreads();
+      if (g == 0) {
+        float st = reds[p];
+#pragma unroll
+        for (int j = 1; j < G; ++j) st += reds[j * T + p];
+        float mref = 0.0f;
+        if (valid && !(st >= 0x1p-100f)) {
+          // far from every component: exact max-shifted sum for this point
+          float m = -INFINITY;
+          for (int bb = 0; bb < K; ++bb)
+            m = fmaxf(m, comp_logterm(cpar + (size_t)bb * kParStride, x.x, x.y, x.z));
+          st = 0.0f;
+          for (int bb = 0; bb < K; ++bb) {
+            const float e = __builtin_amdgcn_exp2f(
+                comp_logterm(cpar + (size_t)bb * kParStride, x.x, x.y, x.z) - m);
+            if (NCH == 1) E[bb * TS + p] = e;
+            st += e;
+          }
+          mref = m;
+        }
+        Xs[p] = make_float4(x.x, x.y, x.z, valid ? 1.0f / st : 0.0f);
+        Mp[p] = mref;
+        if (valid) {
+          const double lse = (Cb + (double)mref + (double)log2f(st)) * kLn2;
+          Lacc += lse;
+          if (lse_out) lse_out[(size_t)tile * T + p] = (float)lse;
+        }
+      }
+    } else if (NCH == 1) {
+      for (int b = b_lo; b < b_hi; ++b) E[b * TS + p] = (b == tag) ? 1.0f : 0.0f;
+      if (g == 0) Xs[p] = make_float4(x.x, x.y, x.z, valid ? 1.0f : 0.0f);
+    } else if (g == 0) {
+      Xs[p] = make_float4(x.x, x.y, x.z, valid ? 1.0f : 0.0f);
+    }
+    if (mode != kSoftLogLik) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int c0 = c * KC;
+        if (NCH > 1) {
+          __syncthreads();  // Xs / Mp ready; previous chunk consumed
+          const int nc = min(KC, K - c0);
+          const int lo = c0 + (g * nc) / G, hi = c0 + ((g + 1) * nc) / G;
+          if (mode == kLabels) {
+            for (int b = lo; b < hi; ++b)
+              E[(b - c0) * TS + p] = (b == tag) ? 1.0f : 0.0f;
+          } else {
+            const float mref = Mp[p];
+            for (int b = lo; b < hi; ++b)
+              E[(b - c0) * TS + p] = __builtin_amdgcn_exp2f(
+                  comp_logterm(cpar + (size_t)b * kParStride, x.x, x.y, x.z) - mref);
+          }
+        }
+        __syncthreads();
+        if (mact && c0 + mb < K)
+          mstep_run<TRIP>(E + mb * TS + mq * trip, Xs + mq * trip, sh[c], acc[c]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- this block's partial row
+  double *row = part + (size_t)blockIdx.x * a.ncols;
+  if (mode != kSoftLogLik) {
+    // sum the P point subsets of each component, one statistic at a time
+    double *D = reinterpret_cast<double *>(smem);  // P x KC
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+      for (int j = 0; j < kNStat; ++j) {
+        __syncthreads();
+        if (mact) D[mq * KC + mb] = acc[c][j];
+        __syncthreads();
+        for (int i = tid; i < KC; i += BLOCK) {
+          const int b = c * KC + i;
+          if (b < K) {
+            double sum = 0.0;
+            for (int qq = 0; qq < P; ++qq) sum += D[qq * KC + i];
+            row[j * K + b] = sum;
+          }
+        }
+      }
+    }
+  }
+  // block sum of the per-point log-normalisers (fixed butterfly order)
+  double v = Lacc;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((tid & 63) == 0) wL[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int j = 0; j < BLOCK / 64; ++j) sum += wL[j];
+    row[kNStat * K] = sum;
+  }
+
+}
+
+// ------------------------------------------------------ reduction kernels
+// Two fence-free launches after each tile pass:
+//  reduce_rows_kernel  red2[y][c] = sum of part[r][c] over the y-th chunk of
+//                      rows; a block owns 64 columns x one chunk, its 4
+//                      waves take interleaved rows and are added in wave
+//                      order (loads issued 4 at a time, adds in row order).
+//  update_kernel       one block: tot[c] = sum_y red2[y][c] in y order, then
+//                      the M-step (em_update_block) from LDS.
+constexpr int kRedChunks = 16;
+constexpr int kUpdThreads = 1024;
+
+__global__ __launch_bounds__(256) void reduce_rows_kernel(
+    const double *__restrict__ part, int nrows, int ncols, int col0,
+    double *__restrict__ red2) {
+  __shared__ double sh[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = col0 + blockIdx.x * 64 + lane;
+  const int cs = (nrows + kRedChunks - 1) / kRedChunks;
+  const int r0 = blockIdx.y * cs, r1 = min(nrows, r0 + cs);
+  double s = 0.0;
+  if (c < ncols) {
+    int r = r0 + wv;
+    for (; r + 12 < r1; r += 16) {
+      const double v0 = part[(size_t)r * ncols + c];
+      const double v1 = part[(size_t)(r + 4) * ncols + c];
+      const double v2 = part[(size_t)(r + 8) * ncols + c];
+      const double v3 = part[(size_t)(r + 12) * ncols + c];
+      s += v0; s += v1; s += v2; s += v3;
+    }
+    for (; r < r1; r += 4) s += part[(size_t)r * ncols + c];
+  }
+  sh[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && c < ncols)
+    red2[(size_t)blockIdx.y * ncols + c] =
+        ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+}
+
+struct UpdArgs {
+  int ncols, col0, K, mode, umode;
+  double reg;
+};
+struct UpdPtrs {
+  const double *red2;
+  const float *cpar_in;
+  const float4 *shift_in;
+  float *cpar_out;
+  float4 *shift_out;
+  double *th64;
+  double *loglik_slot;
+  float *out_w, *out_mu, *out_cov;
+  uint32_t *status;
+};
+
+__global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdPtrs q, UpdArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+  const int K = a.K;
+  double *tot = reinterpret_cast<double *>(smem);  // ncols
+  double *scratch = tot + a.ncols;                 // kUpdThreads
+  double *sN = scratch + kUpdThreads;              // K
+  double *sC = sN + K;                             // K
+  for (int c = a.col0 + tid; c < a.ncols; c += kUpdThreads) {
+    double t = 0.0;
+#pragma unroll
+    for (int y = 0; y < kRedChunks; ++y) t += q.red2[(size_t)y * a.ncols + c];
+    tot[c] = t;
+  }
+  __syncthreads();
+  if (tid == 0 && q.loglik_slot && a.mode != kLabels) {
+    const double L = tot[kNStat * K];
+    q.loglik_slot[0] = L;
+    if (!isfinite(L)) set_status(q.status, kStNonFinite);
+  }
+  if (a.umode != kUpdNone) {
+    em_update_block<kUpdThreads>(tot, K, a.umode, a.reg, q.cpar_in, q.shift_in,
+                                 q.cpar_out, q.shift_out, q.th64, sN, sC,
+                                 scratch, q.status);
+  } else if (q.out_w) {
+    for (int b = tid; b < K; b += kUpdThreads) {
+      const double *t = q.th64 + (size_t)b * kTh64Stride;
+      q.out_w[b] = (float)t[0];
+      for (int j = 0; j < 3; ++j) q.out_mu[3 * b + j] = (float)t[1 + j];
+      float *cv = q.out_cov + 9 * b;
+      cv[0] = (float)t[4];
+      cv[1] = cv[3] = (float)t[5];
+      cv[4] = (float)t[6];
+      cv[2] = cv[6] = (float)t[7];
+      cv[5] = cv[7] = (float)t[8];
+      cv[8] = (float)t[9];
+    }
+  }
+}
+
+inline size_t update_lds_bytes(int K) {
+  return ((size_t)kNStat * K + 1 + kUpdThreads + 2 * (size_t)K) * sizeof(double);
+}
+
+
+// ------------------------------------------------------ registration backward
+// Gradient of L = sum_n lse_n(y_n), y_n = R x_n + t (eq. 2-3 on the moved
+// cloud), one launch over tiles like the forward:
+//  E-phase per (point, component): as the forward, plus u = P'^T z'
+//    (= s^2 Sigma_b^-1 d, s^2 = log2(e)/2) and G_p += e_pb u; after the
+//    per-point normaliser s_p:  g_p = dL/dy_p = -G_p / (s^2 s_p).
+//    dL/dx_p = R^T g_p is written per point; sum g_p and
+//    sum (y_p - t) x g_p are accumulated per lane in FP64.
+//  M-phase: the forward's statistics with the shift mu_b, i.e.
+//    N_b, A_b = sum g d, B_b = sum g d d^T, d = y - mu_b.
+// Row layout: the forward's 10 K + 1 columns, then sum g (3), sum (y-t) x g (3).
+constexpr int kBwdExtra = 6;
+
+template <int BLOCK, int T, int TRIP>
+__global__ __launch_bounds__(BLOCK) void em_bwd_kernel(
+    const float4 *__restrict__ pts, const float *__restrict__ cpar,
+    const float4 *__restrict__ shift, const float *__restrict__ Rt,
+    const double *__restrict__ grad_L, double *__restrict__ part,
+    float *__restrict__ g_pts, TileArgs a, int64_t n_real) {
+  using S = TileShape<BLOCK, T>;
+  constexpr int G = S::G, TS = S::TS;
+  constexpr int trip = TRIP;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int K = a.K, KC = a.KC, P = a.P;
+  float *E = reinterpret_cast<float *>(smem);
+  float4 *Xs = reinterpret_cast<float4 *>(smem + tile_lds_bytes_e<BLOCK, T>(K, KC));
+  float *reds = reinterpret_cast<float *>(Xs + TS);   // G x T
+  float *redg = reds + G * T;                           // 3 x G x T
+  double *wL = reinterpret_cast<double *>(redg + 3 * G * T);  // 7 x BLOCK/64
+
+  const int tid = threadIdx.x;
+  const int p = tid % T;
+  const int g = __builtin_amdgcn_readfirstlane(tid / T);
+  const int b_lo = (g * K) / G;
+  const int b_hi = ((g + 1) * K) / G;
+  const bool mact = tid < KC * P;
+  const int mb = mact ? tid % KC : 0;
+  const int mq = mact ? tid / KC : 0;
+  const double Cb = *reinterpret_cast<const double *>(cpar + (size_t)K * kParStride);
+  const float inv_s2 = (float)(2.0 / kLog2e);
+  const float gl = grad_L ? (float)grad_L[0] : 1.0f;
+  float Rm[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+  float tv[3] = {0.f, 0.f, 0.f};
+  if (Rt) {
+    for (int i = 0; i < 9; ++i) Rm[i] = Rt[i];
+    for (int i = 0; i < 3; ++i) tv[i] = Rt[9 + i];
+  }
+
+  const float4 sh = shift[mb];
+  double acc[kNStat];
+#pragma unroll
+  for (int j = 0; j < kNStat; ++j) acc[j] = 0.0;
+  double Lacc = 0.0, pg[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = tid; b < KC; b += BLOCK) E[b * TS + T] = 0.0f;
+  if (tid < TS - T) Xs[T + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const float4 x = pts[(size_t)tile * T + p];
+    const bool valid = __float_as_int(x.w) >= 0;
+    float s = 0.0f, G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;
+    for (int b = b_lo; b < b_hi; ++b) {
+      const float *q = cpar + (size_t)b * kParStride;
+      const float d0 = x.x - q[0], d1 = x.y - q[1], d2 = x.z - q[2];
+      const float z0 = q[4] * d0;
+      const float z1 = fmaf(q[5], d0, q[6] * d1);
+      const float z2 = fmaf(q[7], d0, fmaf(q[8], d1, q[9] * d2));
+      float l = fmaf(-z0, z0, q[3]);
+      l = fmaf(-z1, z1, l);
+      l = fmaf(-z2, z2, l);
+      const float e = __builtin_amdgcn_exp2f(l);
+      E[b * TS + p] = e;
+      s += e;
+      const float u0 = fmaf(q[4], z0, fmaf(q[5], z1, q[7] * z2));
+      const float u1 = fmaf(q[6], z1, q[8] * z2);
+      const float u2 = q[9] * z2;
+      G0 = fmaf(e, u0, G0);
+      G1 = fmaf(e, u1, G1);
+      G2 = fmaf(e, u2, G2);
+    }
+    reds[g * T + p] = s;
+    redg[(0 * G + g) * T + p] = G0;
+    redg[(1 * G + g) * T + p] = G1;
+    redg[(2 * G + g) * T + p] = G2;
+    __syncthreads();
+    if (g == 0) {
+      float st = reds[p], H0 = redg[p], H1 = redg[G * T + p], H2 = redg[2 * G * T + p];
+#pragma unroll
+      for (int j = 1; j < G; ++j) {
+        st += reds[j * T + p];
+        H0 += redg[(0 * G + j) * T + p];
+        H1 += redg[(1 * G + j) * T + p];
+        H2 += redg[(2 * G + j) * T + p];
+      }
+      float mref = 0.0f;
+      if (valid && !(st >= 0x1p-100f)) {
+        // far from every component: redo the point with its own maximum
+        float m = -INFINITY;
+        for (int bb = 0; bb < K; ++bb)
+          m = fmaxf(m, comp_logterm(cpar + (size_t)bb * kParStride, x.x, x.y, x.z));
+        st = 0.0f; H0 = 0.0f; H1 = 0.0f; H2 = 0.0f;
+        for (int bb = 0; bb < K; ++bb) {
+          const float *q = cpar + (size_t)bb * kParStride;
+          const float d0 = x.x - q[0], d1 = x.y - q[1], d2 = x.z - q[2];
+          const float z0 = q[4] * d0;
+          const float z1 = fmaf(q[5], d0, q[6] * d1);
+          const float z2 = fmaf(q[7], d0, fmaf(q[8], d1, q[9] * d2));
+          const float l = fmaf(-z2, z2, fmaf(-z1, z1, fmaf(-z0, z0, q[3])));
+          const float e = __builtin_amdgcn_exp2f(l - m);
+          E[bb * TS + p] = e;
+          st += e;
+          H0 = fmaf(e, fmaf(q[4], z0, fmaf(q[5], z1, q[7] * z2)), H0);
+          H1 = fmaf(e, fmaf(q[6], z1, q[8] * z2), H1);
+          H2 = fmaf(e, q[9] * z2, H2);
+        }
+        mref = m;
+      }
+      const float r = valid ? 1.0f / st : 0.0f;
+      Xs[p] = make_float4(x.x, x.y, x.z, r);
+      if (valid) {
+        const double lse = (Cb + (double)mref + (double)log2f(st)) * kLn2;
+        Lacc += lse;
+        // g = dL/dy = -Sigma^-1 d weighted = -(H / s_p) / s^2
+        const float c = -r * inv_s2;
+        const float g0 = c * H0, g1 = c * H1, g2 = c * H2;
+        const size_t idx = (size_t)tile * T + p;
+        if (g_pts && idx < (size_t)n_real) {
+          g_pts[3 * idx + 0] = gl * (Rm[0] * g0 + Rm[3] * g1 + Rm[6] * g2);
+          g_pts[3 * idx + 1] = gl * (Rm[1] * g0 + Rm[4] * g1 + Rm[7] * g2);
+          g_pts[3 * idx + 2] = gl * (Rm[2] * g0 + Rm[5] * g1 + Rm[8] * g2);
+        }
+        const float rx = x.x - tv[0], ry = x.y - tv[1], rz = x.z - tv[2];
+        pg[0] += g0; pg[1] += g1; pg[2] += g2;
+        pg[3] += (double)(ry * g2 - rz * g1);
+        pg[4] += (double)(rz * g0 - rx * g2);
+        pg[5] += (double)(rx * g1 - ry * g0);
+      }
+    }
+    __syncthreads();
+    if (mact && mb < K)
+      mstep_run<TRIP>(E + mb * TS + mq * trip, Xs + mq * trip, sh, acc);
+    __syncthreads();
+  }
+
+  double *row = part + (size_t)blockIdx.x * a.ncols;
+  double *D = reinterpret_cast<double *>(smem);  // P x KC
+#pragma unroll
+  for (int j = 0; j < kNStat; ++j) {
+    __syncthreads();
+    if (mact) D[mq * KC + mb] = acc[j];
+    __syncthreads();
+    for (int i = tid; i < K; i += BLOCK) {
+      double sum = 0.0;
+      for (int qq = 0; qq < P; ++qq) sum += D[qq * KC + i];
+      row[j * K + i] = sum;
+    }
+  }
+  // block sums of lse and the six pose terms (fixed butterfly order)
+  double vals[7] = {Lacc, pg[0], pg[1], pg[2], pg[3], pg[4], pg[5]};
+  for (int k = 0; k < 7; ++k) {
+    double v = vals[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((tid & 63) == 0) wL[k * (BLOCK / 64) + (tid >> 6)] = v;
+  }
+  __syncthreads();
+  if (tid < 7) {
+    double sum = 0.0;
+    for (int j = 0; j < BLOCK / 64; ++j) sum += wL[tid * (BLOCK / 64) + j];
+    row[kNStat * K + tid] = sum;
+  }
+}
+
+template <int BLOCK, int T>
+__host__ __device__ constexpr size_t bwd_lds_bytes(int K) {
+  using S = TileShape<BLOCK, T>;
+  return tile_lds_bytes_e<BLOCK, T>(K, K) + S::TS * sizeof(float4) +
+         4 * (size_t)S::G * T * sizeof(float) + 7 * (BLOCK / 64) * sizeof(double);
+}
+
+// Final step of the backward (one block): from the reduced columns and the
+// FP32 mixture (Sigma^-1 = P^T P from an FP64 Cholesky),
+//   dL/dpi_b = N_b / pi_b,  dL/dmu_b = Sigma^-1 A_b,
+//   dL/dSigma_b = 1/2 Sigma^-1 B_b Sigma^-1 - 1/2 N_b Sigma^-1,
+//   dL/dt = sum g,  dL/domega = J_l^T sum (y - t) x g,
+// all times grad_L.
+__global__ __launch_bounds__(256) void bwd_finish_kernel(
+    const double *__restrict__ red2, int ncols, int K,
+    const float *__restrict__ w, const float *__restrict__ cov,
+    const double *__restrict__ pose64, const double *__restrict__ grad_L,
+    float *g_pose6, float *g_w, float *g_mu, float *g_cov, uint32_t *status) {
+  const double gl = grad_L ? grad_L[0] : 1.0;
+  auto col = [&](int c) {
+    double t = 0.0;
+#pragma unroll
+    for (int y = 0; y < kRedChunks; ++y) t += red2[(size_t)y * ncols + c];
+    return t;
+  };
+  for (int b = threadIdx.x; b < K; b += blockDim.x) {
+    const double N = col(b);
+    const double A[3] = {col(K + b), col(2 * K + b), col(3 * K + b)};
+    double Bl[6];
+    for (int j = 0; j < 6; ++j) Bl[j] = col((4 + j) * K + b);
+    const float *c = cov + 9 * b;
+    const double C[6] = {c[0], c[3], c[4], c[6], c[7], c[8]};
+    double L[6], P[6];
+    if (!chol3(C, L)) {
+      set_status(status, kStNotSpd);
+      continue;
+    }
+    tri_inv3(L, P);
+    // Sigma^-1 = P^T P (full symmetric)
+    const double Pm[9] = {P[0], 0.0, 0.0, P[1], P[2], 0.0, P[3], P[4], P[5]};
+    double Si[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double v = 0.0;
+        for (int k = 0; k < 3; ++k) v += Pm[k * 3 + i] * Pm[k * 3 + j];
+        Si[i * 3 + j] = v;
+      }
+    const double B[9] = {Bl[0], Bl[1], Bl[3], Bl[1], Bl[2], Bl[4], Bl[3], Bl[4], Bl[5]};
+    if (g_w) g_w[b] = (float)(gl * N / (double)w[b]);
+    if (g_mu)
+      for (int i = 0; i < 3; ++i)
+        g_mu[3 * b + i] = (float)(gl * (Si[i * 3] * A[0] + Si[i * 3 + 1] * A[1] + Si[i * 3 + 2] * A[2]));
+    if (g_cov) {
+      double T1[9];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double v = 0.0;
+          for (int k = 0; k < 3; ++k) v += Si[i * 3 + k] * B[k * 3 + j];
+          T1[i * 3 + j] = v;
+        }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double v = 0.0;
+          for (int k = 0; k < 3; ++k) v += T1[i * 3 + k] * Si[k * 3 + j];
+          g_cov[9 * b + i * 3 + j] = (float)(gl * (0.5 * v - 0.5 * N * Si[i * 3 + j]));
+        }
+    }
+  }
+  if (threadIdx.x == 0 && g_pose6) {
+    const int c0 = kNStat * K + 1;
+    const double gs[3] = {col(c0), col(c0 + 1), col(c0 + 2)};
+    const double h[3] = {col(c0 + 3), col(c0 + 4), col(c0 + 5)};
+    double J[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    if (pose64)
+      for (int i = 0; i < 9; ++i) J[i] = pose64[12 + i];
+    for (int i = 0; i < 3; ++i) {
+      g_pose6[i] = (float)(gl * (J[i] * h[0] + J[3 + i] * h[1] + J[6 + i] * h[2]));
+      g_pose6[3 + i] = (float)(gl * gs[i]);
+    }
+    if (!isfinite(gs[0] + gs[1] + gs[2] + h[0] + h[1] + h[2]))
+      set_status(status, kStNonFinite);
+  }
+}
+
+}  // namespace gmm_dev

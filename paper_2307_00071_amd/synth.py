@@ -109,9 +109,12 @@ def _ray_vcyl(o, d, cxy, r, z0, z1):
 
 def depth_frame(seed: int = 0, width: int = 640, height: int = 480,
                 fx: float = 525.0, fy: float = 525.0, cx: float = 319.5,
-                cy: float = 239.5, sigma: float = 0.01) -> np.ndarray:
+                cy: float = 239.5, sigma: float = 0.01,
+                noise_seed=None) -> np.ndarray:
     """One synthetic depth frame in the camera frame (x right, y down,
-    z forward).  Returns float32 (width*height, 3); every ray hits."""
+    z forward).  Returns float32 (width*height, 3); every ray hits.
+    ``noise_seed`` (optional) draws the range noise from its own generator:
+    a second noisy render of the same scene."""
     rng = np.random.default_rng(seed)
     u, v = np.meshgrid(np.arange(width, dtype=np.float64),
                        np.arange(height, dtype=np.float64))
@@ -143,7 +146,8 @@ def depth_frame(seed: int = 0, width: int = 640, height: int = 480,
                            rng.uniform(0.2, 1.2), rng.uniform(0.2, 1.2))
         t = np.minimum(t, th)
     assert np.all(np.isfinite(t))
-    t = t + sigma * rng.standard_normal(t.shape)
+    nrng = rng if noise_seed is None else np.random.default_rng(noise_seed)
+    t = t + sigma * nrng.standard_normal(t.shape)
     return (t[:, None] * d).astype(np.float32)
 
 

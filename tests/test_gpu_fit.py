@@ -276,3 +276,33 @@ def test_loglik_matches_oracle_with_pose():
     L0 = gmm.loglik(_to(X), *(_to(a) for a in th))
     Lr0 = oracle.loglik_pose(X, None, *th)
     assert abs(L0.item() - Lr0) <= 1e-5 * max(abs(Lr0), X.shape[0])
+
+
+def test_graph_replay_matches_direct_launches():
+    """Repeated fits with identical buffers are captured into a hipGraph on
+    the second call and replayed afterwards; every call must agree bitwise
+    with the first (direct-launch) call, with eager torch work and
+    synchronisations between the calls."""
+    _case("graph replay")
+    X = _depth_subset(40000, seed=11)
+    lab = synth.kmeanspp_labels(X, 32, 2)
+    pts = _to(X)
+    labt = _to(lab, torch.int32)
+    ws = torch.empty(gmm.fit_workspace_bytes(X.shape[0], 32, 8), dtype=torch.uint8,
+                     device=DEV)
+    other = torch.randn(1 << 20, device=DEV)
+    outs = []
+    for i in range(4):
+        r = gmm.fit(pts, 32, iters=8, reg_covar=1e-3, labels=labt, workspace=ws)
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy().copy() for t in r])
+        float(other.sum())          # eager work between replays
+        torch.cuda.synchronize()
+    for o in outs[1:]:
+        for u, v in zip(outs[0], o):
+            np.testing.assert_array_equal(u, v)
+    # a changed input behind the same pointer is read at replay time
+    pts.mul_(1.0001)
+    r = gmm.fit(pts, 32, iters=8, reg_covar=1e-3, labels=labt, workspace=ws)
+    torch.cuda.synchronize()
+    assert not np.array_equal(r.means.cpu().numpy(), outs[0][1])
