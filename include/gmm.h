@@ -155,10 +155,37 @@ gmm_status gmm_loglik_backward(const float *pts, int64_t n, const float *pose6,
                                float *g_mu, float *g_cov, void *ws,
                                size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------ batching
+ * gmm_fit_batched: B independent fits (same options) in one submission.
+ *  pts          device float32, the frames' points concatenated (sum N_f x 3).
+ *  pt_off       HOST int64 B + 1: frame f owns points [pt_off[f], pt_off[f+1]),
+ *               pt_off[0] = 0.
+ *  k_off        HOST int32 B + 1: frame f owns components [k_off[f], k_off[f+1]),
+ *               k_off[0] = 0; 1 <= K_f <= min(N_f, 512).
+ *  init_labels  device int32, concatenated per-frame labels in [0, K_f), or
+ *               NULL (then w/mu/cov hold every frame's theta_0).
+ *  w, mu, cov   device float32 sum K_f, x 3, x 3 x 3 (concatenated).
+ *  loglik       device float64 B x (iters + 1) (row f = frame f), or NULL.
+ * Every frame follows gmm_fit exactly (same E-step, M-step and per-frame
+ * reductions); the frames' work is spread over the GPU by one launch per
+ * M-phase class and iteration, with the whole loop captured in a hipGraph.
+ * Synchronises once (twice with the plan upload) unless GMM_FLAG_ASYNC.
+ * Errors: as gmm_fit, per frame. */
+size_t gmm_fit_batched_workspace_size(int32_t B, const int64_t *pt_off,
+                                      const int32_t *k_off,
+                                      const gmm_fit_opts *opts);
+
+gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
+                           const int32_t *k_off, const int32_t *init_labels,
+                           float *w, float *mu, float *cov, double *loglik,
+                           const gmm_fit_opts *opts, void *ws, size_t ws_bytes,
+                           void *stream);
+
 /* ------------------------------------------------------------ profiling
  * Kernel timing for benchmarks.  While enabled (per calling host thread),
  * every E+M statistics launch of the tile kernel made by gmm_fit is
- * bracketed by two HIP events recorded on the caller's stream.
+ * bracketed by two HIP events recorded on the caller's stream (such calls
+ * launch their kernels directly instead of replaying a captured graph).
  * gmm_profile_read waits for the recorded events, returns the summed
  * kernel time (ms) and the launch count since the last read, and resets
  * them.  Errors: DEVICE when an event call fails. */

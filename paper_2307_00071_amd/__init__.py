@@ -13,7 +13,8 @@ import ctypes
 
 from . import _lib
 
-__all__ = ["fit", "loglik", "loglik_backward", "GMMLogLik", "FitResult"]
+__all__ = ["fit", "fit_batched", "loglik", "loglik_backward", "GMMLogLik",
+           "FitResult"]
 
 
 def _torch():
@@ -101,6 +102,74 @@ def fit(points, k, iters=100, reg_covar=1e-3, labels=None, theta0=None,
                      _stream(dev))
     _lib.check(st)
     return FitResult(w, mu, cov, L)
+
+
+def fit_batched(points_list, ks, iters=100, reg_covar=1e-3, labels_list=None,
+                theta0_list=None, moment_mode="shifted", workspace=None):
+    """Fit one GMM per frame, all frames in one batched submission.
+
+    points_list: float32 (N_f, 3) CUDA tensors; ks: K_f per frame; start
+    from per-frame hard labels or theta0 = (w, mu, cov) per frame.  Returns
+    one FitResult per frame (views into concatenated outputs)."""
+    import numpy as np
+    torch = _torch()
+    lib = _lib.load()
+    B = len(points_list)
+    if B == 0 or len(ks) != B:
+        raise ValueError("need one K per frame")
+    dev = points_list[0].device
+    pts = torch.cat([_check_points(p) for p in points_list]).contiguous()
+    pt_off = np.zeros(B + 1, np.int64)
+    pt_off[1:] = np.cumsum([p.shape[0] for p in points_list])
+    k_off = np.zeros(B + 1, np.int32)
+    k_off[1:] = np.cumsum(ks)
+    Kt = int(k_off[-1])
+    opts = _lib.FitOpts(int(iters), float(reg_covar),
+                        {"shifted": 0, "two_pass": 1}[moment_mode], 0)
+    if labels_list is not None:
+        lab = torch.cat([l.to(device=dev, dtype=torch.int32) for l in labels_list]).contiguous()
+        w = torch.empty(Kt, dtype=torch.float32, device=dev)
+        mu = torch.empty(Kt, 3, dtype=torch.float32, device=dev)
+        cov = torch.empty(Kt, 3, 3, dtype=torch.float32, device=dev)
+    elif theta0_list is not None:
+        lab = None
+        w = torch.cat([t[0].to(device=dev, dtype=torch.float32) for t in theta0_list]).contiguous()
+        mu = torch.cat([t[1].to(device=dev, dtype=torch.float32) for t in theta0_list]).contiguous()
+        cov = torch.cat([t[2].to(device=dev, dtype=torch.float32) for t in theta0_list]).contiguous()
+    else:
+        raise ValueError("give labels_list or theta0_list")
+    L = torch.empty(B, iters + 1, dtype=torch.float64, device=dev)
+    po = pt_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    ko = k_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    need = lib.gmm_fit_batched_workspace_size(B, po, ko, ctypes.byref(opts))
+    if need == 0:
+        _lib.check(lib.gmm_fit_batched(B, None, po, ko, None, None, None, None,
+                                       None, ctypes.byref(opts), None, 0, None))
+    ws = workspace if workspace is not None and workspace.numel() >= need \
+        else _workspace(need, dev)
+    _lib.check(lib.gmm_fit_batched(B, _ptr(pts), po, ko, _ptr(lab), _ptr(w),
+                                   _ptr(mu), _ptr(cov), _ptr(L),
+                                   ctypes.byref(opts), _ptr(ws), ws.numel(),
+                                   _stream(dev)))
+    out = []
+    for f in range(B):
+        a, b = int(k_off[f]), int(k_off[f + 1])
+        out.append(FitResult(w[a:b], mu[a:b], cov[a:b], L[f]))
+    return out
+
+
+def fit_batched_workspace_bytes(ns, ks, iters=100):
+    import numpy as np
+    lib = _lib.load()
+    B = len(ns)
+    pt_off = np.zeros(B + 1, np.int64)
+    pt_off[1:] = np.cumsum(ns)
+    k_off = np.zeros(B + 1, np.int32)
+    k_off[1:] = np.cumsum(ks)
+    opts = _lib.FitOpts(int(iters), 1e-3, 0, 0)
+    return int(lib.gmm_fit_batched_workspace_size(
+        B, pt_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        k_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(opts)))
 
 
 def fit_workspace_bytes(n, k, iters=100, reg_covar=1e-3, moment_mode="shifted"):

@@ -23,6 +23,7 @@ EXPORTS = (
     "gmm_fit_workspace_size", "gmm_fit",
     "gmm_loglik_workspace_size", "gmm_loglik",
     "gmm_loglik_backward_workspace_size", "gmm_loglik_backward",
+    "gmm_fit_batched_workspace_size", "gmm_fit_batched",
     "gmm_profile_enable", "gmm_profile_read",
 )
 
@@ -72,6 +73,14 @@ def load():
     lib.gmm_loglik_backward.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp, vp,
                                         vp, vp, vp, vp, vp, sz, vp]
     lib.gmm_loglik_backward.restype = ctypes.c_int
+    lib.gmm_fit_batched_workspace_size.argtypes = [
+        i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+        ctypes.POINTER(FitOpts)]
+    lib.gmm_fit_batched_workspace_size.restype = sz
+    lib.gmm_fit_batched.argtypes = [
+        i32, vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+        vp, vp, vp, vp, vp, ctypes.POINTER(FitOpts), vp, sz, vp]
+    lib.gmm_fit_batched.restype = ctypes.c_int
     lib.gmm_profile_enable.argtypes = [ctypes.c_int]
     lib.gmm_profile_enable.restype = ctypes.c_int
     lib.gmm_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double),

@@ -717,6 +717,266 @@ inline size_t update_lds_bytes(int K) {
 }
 
 
+
+// ---------------------------------------------------------- batched fits
+// Many frames with their own N_f and K_f in one launch per M-phase class:
+// the host cuts the concatenated tiles of the class's frames into one
+// contiguous, cost-balanced range per block (cost = tiles x K_f), split into
+// segments at frame boundaries; each segment writes one partial row of its
+// frame.  A frame's rows are then added in row order by reduce_frames_kernel
+// and update_frames_kernel runs one FP64 M-step per frame (one block each).
+struct BFrame {
+  long long poff;   // first double of the frame's partial rows
+  long long toff;   // first staged tile
+  int K;            // components
+  int koff;         // first component (shift, FP64 state, outputs)
+  int cpoff;        // first float of the frame's E-step block (K + 1 blocks)
+  int P;            // M-phase point subsets
+  int ncols;        // 10 K + 1
+  int nrows;        // partial rows (segments)
+  int roff;         // first column of the frame in the reduced array
+  int pad;
+};
+struct BSeg {
+  int frame, t0, t1, row;   // staged tiles [t0, t1) of one frame
+};
+
+template <int BLOCK, int T, int TRIP>
+__global__ __launch_bounds__(BLOCK) void em_batch_kernel(
+    const float4 *__restrict__ pts, const float *__restrict__ cpar_all,
+    const float4 *__restrict__ shift_all, double *__restrict__ part,
+    const BFrame *__restrict__ frames, const BSeg *__restrict__ segs,
+    const int *__restrict__ blk_seg, int mode, int kc_max) {
+  using S = TileShape<BLOCK, T>;
+  constexpr int G = S::G, TS = S::TS;
+  extern __shared__ __align__(16) unsigned char smem[];
+  float *E = reinterpret_cast<float *>(smem);
+  float4 *Xs = reinterpret_cast<float4 *>(smem + tile_lds_bytes_e<BLOCK, T>(kc_max, kc_max));
+  float *reds = reinterpret_cast<float *>(Xs + TS);
+  double *wL = reinterpret_cast<double *>(reds + G * T + T);
+
+  const int tid = threadIdx.x;
+  const int p = tid % T;
+  const int g = __builtin_amdgcn_readfirstlane(tid / T);
+  for (int b = tid; b < kc_max; b += BLOCK) E[b * TS + T] = 0.0f;
+  if (tid < TS - T) Xs[T + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+  const int s0 = blk_seg[blockIdx.x], s1 = blk_seg[blockIdx.x + 1];
+  for (int si = s0; si < s1; ++si) {
+    const BSeg sg = segs[si];
+    const BFrame F = frames[sg.frame];
+    const int K = F.K, P = F.P;
+    const float *cpar = cpar_all + F.cpoff;
+    const double Cb = *reinterpret_cast<const double *>(cpar + (size_t)K * kParStride);
+    const int b_lo = (g * K) / G;
+    const int b_hi = ((g + 1) * K) / G;
+    const bool mact = tid < K * P;
+    const int mb = mact ? tid % K : 0;
+    const int mq = mact ? tid / K : 0;
+    const float4 sh = shift_all[F.koff + mb];
+    double acc[kNStat];
+#pragma unroll
+    for (int j = 0; j < kNStat; ++j) acc[j] = 0.0;
+    double Lacc = 0.0;
+    for (int tile = sg.t0; tile < sg.t1; ++tile) {
+      const float4 x = pts[(size_t)tile * T + p];
+      const int tag = __float_as_int(x.w);
+      const bool valid = tag >= 0;
+      if (mode != kLabels) {
+        float s = 0.0f;
+        const float *q = cpar + (size_t)b_lo * kParStride;
+        float *Ep = E + (size_t)b_lo * TS + p;
+        int b = b_lo;
+        for (; b + 4 <= b_hi; b += 4, q += 4 * kParStride, Ep += 4 * TS) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float e = __builtin_amdgcn_exp2f(
+                comp_logterm(q + u * kParStride, x.x, x.y, x.z));
+            Ep[u * TS] = e;
+            s += e;
+          }
+        }
+        for (; b < b_hi; ++b, q += kParStride, Ep += TS) {
+          const float e = __builtin_amdgcn_exp2f(comp_logterm(q, x.x, x.y, x.z));
+          *Ep = e;
+          s += e;
+        }
+        reds[g * T + p] = s;
+        __syncthreads();
+        if (g == 0) {
+          float st = reds[p];
+#pragma unroll
+          for (int j = 1; j < G; ++j) st += reds[j * T + p];
+          float mref = 0.0f;
+          if (valid && !(st >= 0x1p-100f)) {
+            float m = -INFINITY;
+            for (int bb = 0; bb < K; ++bb)
+              m = fmaxf(m, comp_logterm(cpar + (size_t)bb * kParStride, x.x, x.y, x.z));
+            st = 0.0f;
+            for (int bb = 0; bb < K; ++bb) {
+              const float e = __builtin_amdgcn_exp2f(
+                  comp_logterm(cpar + (size_t)bb * kParStride, x.x, x.y, x.z) - m);
+              E[bb * TS + p] = e;
+              st += e;
+            }
+            mref = m;
+          }
+          Xs[p] = make_float4(x.x, x.y, x.z, valid ? 1.0f / st : 0.0f);
+          if (valid) Lacc += (Cb + (double)mref + (double)log2f(st)) * kLn2;
+        }
+      } else {
+        for (int b = b_lo; b < b_hi; ++b) E[b * TS + p] = (b == tag) ? 1.0f : 0.0f;
+        if (g == 0) Xs[p] = make_float4(x.x, x.y, x.z, valid ? 1.0f : 0.0f);
+      }
+      __syncthreads();
+      if (mode != kSoftLogLik && mact)
+        mstep_run<TRIP>(E + mb * TS + mq * TRIP, Xs + mq * TRIP, sh, acc);
+      __syncthreads();
+    }
+    // this segment's row of its frame
+    double *row = part + F.poff + (size_t)sg.row * F.ncols;
+    if (mode != kSoftLogLik) {
+      double *D = reinterpret_cast<double *>(smem);  // P x K
+#pragma unroll
+      for (int j = 0; j < kNStat; ++j) {
+        __syncthreads();
+        if (mact) D[mq * K + mb] = acc[j];
+        __syncthreads();
+        for (int i = tid; i < K; i += BLOCK) {
+          double sum = 0.0;
+          for (int qq = 0; qq < P; ++qq) sum += D[qq * K + i];
+          row[j * K + i] = sum;
+        }
+      }
+    }
+    double v = Lacc;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((tid & 63) == 0) wL[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0.0;
+      for (int j = 0; j < BLOCK / 64; ++j) sum += wL[j];
+      row[kNStat * K] = sum;
+    }
+    __syncthreads();   // E, D and wL are reused by the next segment
+    // D overwrote the start of E: restore the zero pad column (the next
+    // segment's first barrier orders these stores before any M-phase read)
+    for (int b = tid; b < kc_max; b += BLOCK) E[b * TS + T] = 0.0f;
+  }
+}
+
+template <int BLOCK, int T>
+__host__ __device__ constexpr size_t batch_lds_bytes(int kc_max) {
+  using S = TileShape<BLOCK, T>;
+  return tile_lds_bytes_e<BLOCK, T>(kc_max, kc_max) + S::TS * sizeof(float4) +
+         ((size_t)S::G * T + T) * sizeof(float) + (BLOCK / 64) * sizeof(double);
+}
+
+// red[frame roff + c] = sum over the frame's rows of part[row][c], rows
+// added in order by 4 interleaved waves then in wave order.
+__global__ __launch_bounds__(256) void reduce_frames_kernel(
+    const double *__restrict__ part, const BFrame *__restrict__ frames,
+    int only_L, double *__restrict__ red) {
+  __shared__ double sh[4][64];
+  const BFrame F = frames[blockIdx.x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col0 = only_L ? kNStat * F.K : 0;
+  const int c = col0 + blockIdx.y * 64 + lane;
+  if (col0 + blockIdx.y * 64 >= F.ncols) return;   // uniform per block
+  double s = 0.0;
+  if (c < F.ncols) {
+    const double *base = part + F.poff + c;
+    int r = wv;
+    for (; r + 12 < F.nrows; r += 16) {
+      const double v0 = base[(size_t)r * F.ncols];
+      const double v1 = base[(size_t)(r + 4) * F.ncols];
+      const double v2 = base[(size_t)(r + 8) * F.ncols];
+      const double v3 = base[(size_t)(r + 12) * F.ncols];
+      s += v0; s += v1; s += v2; s += v3;
+    }
+    for (; r < F.nrows; r += 4) s += base[(size_t)r * F.ncols];
+  }
+  sh[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && c < F.ncols)
+    red[F.roff + c] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+}
+
+// One block per frame: the M-step of em_update_block on that frame's
+// reduced columns (or, with kUpdNone, its log-likelihood and FP32 outputs).
+__global__ __launch_bounds__(kUpdThreads) void update_frames_kernel(
+    const double *__restrict__ red, const BFrame *__restrict__ frames,
+    int mode, int umode, double reg, const float *cpar_in,
+    const float4 *shift_in, float *cpar_out, float4 *shift_out, double *th64,
+    double *loglik, int ll_stride, int ll_index, float *out_w, float *out_mu,
+    float *out_cov, uint32_t *status) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BFrame F = frames[blockIdx.x];
+  const int K = F.K, tid = threadIdx.x;
+  double *tot = reinterpret_cast<double *>(smem);   // ncols
+  double *scratch = tot + F.ncols;                  // kUpdThreads
+  double *sN = scratch + kUpdThreads;               // K
+  double *sC = sN + K;                              // K
+  const int col0 = (mode == kSoftLogLik) ? kNStat * K : 0;
+  for (int c = col0 + tid; c < F.ncols; c += kUpdThreads) tot[c] = red[F.roff + c];
+  __syncthreads();
+  if (tid == 0 && loglik && mode != kLabels) {
+    const double L = tot[kNStat * K];
+    loglik[(size_t)blockIdx.x * ll_stride + ll_index] = L;
+    if (!isfinite(L)) set_status(status, kStNonFinite);
+  }
+  double *t64 = th64 + (size_t)F.koff * kTh64Stride;
+  if (umode != kUpdNone) {
+    em_update_block<kUpdThreads>(tot, K, umode, reg, cpar_in + F.cpoff,
+                                 shift_in + F.koff, cpar_out + F.cpoff,
+                                 shift_out + F.koff, t64, sN, sC, scratch,
+                                 status);
+  } else if (out_w) {
+    for (int b = tid; b < K; b += kUpdThreads) {
+      const double *t = t64 + (size_t)b * kTh64Stride;
+      const int gb = F.koff + b;
+      out_w[gb] = (float)t[0];
+      for (int j = 0; j < 3; ++j) out_mu[3 * gb + j] = (float)t[1 + j];
+      float *cv = out_cov + 9 * gb;
+      cv[0] = (float)t[4];
+      cv[1] = cv[3] = (float)t[5];
+      cv[4] = (float)t[6];
+      cv[2] = cv[6] = (float)t[7];
+      cv[5] = cv[7] = (float)t[8];
+      cv[8] = (float)t[9];
+    }
+  }
+}
+
+// Caller-supplied theta_0 for every frame (one block per frame).
+__global__ __launch_bounds__(kPreThreads) void precompute_frames_kernel(
+    const float *__restrict__ w, const float *__restrict__ mu,
+    const float *__restrict__ cov, const BFrame *__restrict__ frames,
+    float *cpar_all, float4 *shift_all, double *th64, uint32_t *status) {
+  __shared__ double scratch[kPreThreads];
+  __shared__ double sC[GMM_MAX_K];
+  const BFrame F = frames[blockIdx.x];
+  float *cpar = cpar_all + F.cpoff;
+  float4 *shift = shift_all + F.koff;
+  double *t64 = th64 + (size_t)F.koff * kTh64Stride;
+  for (int b = threadIdx.x; b < F.K; b += kPreThreads) {
+    const int gb = F.koff + b;
+    double pi = w[gb];
+    double m[3] = {mu[3 * gb], mu[3 * gb + 1], mu[3 * gb + 2]};
+    const float *c = cov + 9 * gb;
+    double C[6] = {c[0], c[3], c[4], c[6], c[7], c[8]};
+    if (!(pi > 0.0) || !isfinite(pi) || !isfinite(m[0]) || !isfinite(m[1]) ||
+        !isfinite(m[2])) {
+      set_status(status, kStBadArg);
+      pi = 1.0;
+    }
+    const double cc = component_terms(b, pi, m, C, 0.0, cpar, shift, t64);
+    if (!isfinite(cc)) set_status(status, kStNotSpd);
+    sC[b] = cc;
+  }
+  apply_bound<kPreThreads>(F.K, sC, cpar, scratch);
+}
+
 // ------------------------------------------------------ registration backward
 // Gradient of L = sum_n lse_n(y_n), y_n = R x_n + t (eq. 2-3 on the moved
 // cloud), one launch over tiles like the forward:

@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <vector>
 
@@ -44,9 +45,7 @@ gmm_status fail(gmm_status s, const char *fmt, ...) {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Per-thread kernel timing (gmm_profile_*): event pairs around the E+M
-// statistics launches.  Pairs of direct launches wait in `pending`; pairs
-// recorded inside a captured graph belong to that graph and are added to
-// the totals after each replay.
+// statistics launches wait in `pending` until gmm_profile_read.
 struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
 };
@@ -504,12 +503,11 @@ struct FitKey {
   size_t ws_bytes;
   double reg;
   int k, iters, mode, dev;
-  bool prof;
   bool operator==(const FitKey &o) const {
     return pts == o.pts && labels == o.labels && w == o.w && mu == o.mu &&
            cov == o.cov && loglik == o.loglik && ws == o.ws && n == o.n &&
            ws_bytes == o.ws_bytes && reg == o.reg && k == o.k &&
-           iters == o.iters && mode == o.mode && dev == o.dev && prof == o.prof;
+           iters == o.iters && mode == o.mode && dev == o.dev;
   }
 };
 
@@ -517,7 +515,6 @@ struct GraphEntry {
   bool used = false;
   FitKey key{};
   hipGraphExec_t exec = nullptr;
-  std::vector<EventPair> pairs;
   uint64_t stamp = 0;
 };
 
@@ -549,7 +546,6 @@ void release_entry(GraphEntry &e) {
     (void)hipDeviceSynchronize();  // an evicted graph may still be running
     (void)hipGraphExecDestroy(e.exec);
   }
-  destroy_pairs(e.pairs);
   e = GraphEntry{};
 }
 
@@ -570,6 +566,256 @@ GraphEntry *graph_slot(const FitKey &key, bool *found) {
   victim->key = key;
   victim->stamp = ++g_graph_clock;
   return victim;
+}
+
+
+// ============================================================ batched fits
+
+constexpr int kBatchBlock = 512;
+constexpr int kBatchT = 64;
+
+struct BatchClass {
+  int trip = 0, kc_max = 0, grid = 0;
+  size_t lds = 0;
+  std::vector<BSeg> segs;
+  std::vector<int> blk;   // grid + 1 segment offsets
+  size_t seg_off = 0, blk_off = 0;   // byte offsets in the plan upload
+  void (*launch)(const BatchClass &, hipStream_t, const float4 *, const float *,
+                 const float4 *, double *, const BFrame *, const BSeg *,
+                 const int *, int) = nullptr;
+};
+
+template <int TRIP>
+void launch_batch(const BatchClass &c, hipStream_t s, const float4 *pts,
+                  const float *cpar, const float4 *shift, double *part,
+                  const BFrame *frames, const BSeg *segs, const int *blk,
+                  int mode) {
+  hipLaunchKernelGGL((em_batch_kernel<kBatchBlock, kBatchT, TRIP>), dim3(c.grid),
+                     dim3(kBatchBlock), c.lds, s, pts, cpar, shift, part,
+                     frames, segs, blk, mode, c.kc_max);
+}
+
+bool batch_instance(int trip, decltype(BatchClass::launch) *fn, const void **kfn) {
+#define GMM_BATCH_CASE(TR)                                                    \
+  case TR:                                                                   \
+    *fn = &launch_batch<TR>;                                                 \
+    *kfn = reinterpret_cast<const void *>(&em_batch_kernel<kBatchBlock, kBatchT, TR>); \
+    return true;
+  switch (trip) {
+    GMM_BATCH_CASE(1) GMM_BATCH_CASE(2) GMM_BATCH_CASE(4) GMM_BATCH_CASE(5)
+    GMM_BATCH_CASE(8) GMM_BATCH_CASE(13) GMM_BATCH_CASE(16) GMM_BATCH_CASE(32)
+    GMM_BATCH_CASE(64)
+    default: return false;
+  }
+#undef GMM_BATCH_CASE
+}
+
+// Host plan of a batched fit: frame table, per-class cost-balanced tile
+// ranges cut into per-frame segments, and the workspace layout.
+struct BatchPlan {
+  int B = 0, Ktot = 0, Kmax = 0, ncols_max = 0;
+  int64_t tiles = 0;
+  std::vector<BFrame> frames;
+  std::vector<BatchClass> classes;
+  size_t plan_bytes = 0;
+  // workspace offsets
+  size_t status, plan, cpar[2], shift[2], th64, red, part, pts4, total;
+  size_t red_len = 0, part_len = 0;
+};
+
+gmm_status make_batch_plan(int B, const int64_t *pt_off, const int32_t *k_off,
+                           BatchPlan *bp) {
+  DevInfo di = dev_info();
+  if (di.cus <= 0) return fail(GMM_ERR_DEVICE, "no HIP device");
+  if (B <= 0) return fail(GMM_ERR_INVALID_ARG, "B=%d must be positive", B);
+  bp->B = B;
+  bp->frames.assign(B, BFrame{});
+  int64_t toff = 0;
+  int cpoff = 0, roff = 0;
+  for (int f = 0; f < B; ++f) {
+    const int64_t n = pt_off[f + 1] - pt_off[f];
+    const int K = k_off[f + 1] - k_off[f];
+    if (n <= 0 || K <= 0 || K > n)
+      return fail(GMM_ERR_INVALID_ARG, "frame %d: n=%lld k=%d", f, (long long)n, K);
+    if (K > kBatchBlock) return fail(GMM_ERR_UNSUPPORTED, "frame %d: k=%d above %d", f, K, kBatchBlock);
+    BFrame &F = bp->frames[f];
+    F.K = K;
+    F.koff = k_off[f] - k_off[0];
+    F.cpoff = cpoff;
+    cpoff += (K + 1) * kParStride;
+    F.P = pick_subsets(kBatchBlock / K, kBatchT);
+    F.ncols = kNStat * K + 1;
+    F.roff = roff;
+    roff += F.ncols;
+    F.toff = toff;
+    toff += (n + kBatchT - 1) / kBatchT;
+    bp->Kmax = std::max(bp->Kmax, K);
+    bp->ncols_max = std::max(bp->ncols_max, F.ncols);
+  }
+  bp->Ktot = k_off[B] - k_off[0];
+  bp->tiles = toff;
+  bp->red_len = roff;
+  // classes by M-phase trip
+  std::vector<int> trips;
+  for (auto &F : bp->frames) {
+    const int tr = (kBatchT + F.P - 1) / F.P;
+    if (std::find(trips.begin(), trips.end(), tr) == trips.end()) trips.push_back(tr);
+  }
+  std::sort(trips.begin(), trips.end());
+  std::vector<int> nrows(B, 0);
+  for (int tr : trips) {
+    BatchClass c;
+    c.trip = tr;
+    std::vector<int> fr;
+    for (int f = 0; f < B; ++f)
+      if ((kBatchT + bp->frames[f].P - 1) / bp->frames[f].P == tr) {
+        fr.push_back(f);
+        c.kc_max = std::max(c.kc_max, bp->frames[f].K);
+      }
+    c.lds = batch_lds_bytes<kBatchBlock, kBatchT>(c.kc_max);
+    const void *kfn = nullptr;
+    if (!batch_instance(tr, &c.launch, &kfn)) return fail(GMM_ERR_UNSUPPORTED, "no batch kernel for trip %d", tr);
+    if (c.lds > 65536 &&
+        hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds) != hipSuccess)
+      return fail(GMM_ERR_DEVICE, "LDS attribute");
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kBatchBlock, c.lds) != hipSuccess || per_cu <= 0)
+      return fail(GMM_ERR_DEVICE, "occupancy query failed");
+    int64_t ctiles = 0;
+    double cost = 0.0;
+    for (int f : fr) {
+      const int64_t nt = (pt_off[f + 1] - pt_off[f] + kBatchT - 1) / kBatchT;
+      ctiles += nt;
+      cost += (double)nt * bp->frames[f].K;
+    }
+    c.grid = (int)std::min<int64_t>(ctiles, (int64_t)di.cus * per_cu);
+    // walk the class's tiles, cutting block ranges at equal cost
+    const double target = cost / c.grid;
+    double acc = 0.0;
+    int blk = 0;
+    c.blk.push_back(0);
+    for (int f : fr) {
+      const BFrame &F = bp->frames[f];
+      const int64_t nt = (pt_off[f + 1] - pt_off[f] + kBatchT - 1) / kBatchT;
+      int64_t t = 0;
+      while (t < nt) {
+        // tiles this block can still take before reaching its cut
+        const double room = (blk + 1) * target - acc;
+        int64_t take = (int64_t)std::ceil(room / F.K - 1e-9);
+        if (blk == c.grid - 1) take = nt - t;
+        take = std::max<int64_t>(1, std::min<int64_t>(take, nt - t));
+        c.segs.push_back(BSeg{f, (int)(F.toff + t), (int)(F.toff + t + take), nrows[f]++});
+        t += take;
+        acc += (double)take * F.K;
+        if (acc >= (blk + 1) * target - 1e-6 && blk < c.grid - 1) {
+          ++blk;
+          c.blk.push_back((int)c.segs.size());
+        }
+      }
+    }
+    while ((int)c.blk.size() < c.grid + 1) c.blk.push_back((int)c.segs.size());
+    bp->classes.push_back(std::move(c));
+  }
+  int64_t poff = 0;
+  for (int f = 0; f < B; ++f) {
+    bp->frames[f].nrows = nrows[f];
+    bp->frames[f].poff = poff;
+    poff += (int64_t)nrows[f] * bp->frames[f].ncols;
+  }
+  bp->part_len = poff;
+  // plan upload layout
+  size_t o = align256(sizeof(BFrame) * B);
+  for (auto &c : bp->classes) {
+    c.seg_off = o;
+    o = align256(o + sizeof(BSeg) * c.segs.size());
+    c.blk_off = o;
+    o = align256(o + sizeof(int) * c.blk.size());
+  }
+  bp->plan_bytes = o;
+  // workspace
+  o = 0;
+  bp->status = o; o = align256(o + 256);
+  bp->plan = o; o = align256(o + bp->plan_bytes);
+  const size_t npar = (size_t)(bp->Ktot + B) * kParStride;
+  for (int i = 0; i < 2; ++i) {
+    bp->cpar[i] = o; o = align256(o + npar * sizeof(float));
+    bp->shift[i] = o; o = align256(o + (size_t)bp->Ktot * sizeof(float4));
+  }
+  bp->th64 = o; o = align256(o + (size_t)bp->Ktot * kTh64Stride * sizeof(double));
+  bp->red = o; o = align256(o + bp->red_len * sizeof(double));
+  bp->part = o; o = align256(o + bp->part_len * sizeof(double));
+  bp->pts4 = o; o = align256(o + (size_t)bp->tiles * kBatchT * sizeof(float4));
+  bp->total = o;
+  return GMM_OK;
+}
+
+struct BatchRun {
+  const BatchPlan *bp = nullptr;
+  void *ws = nullptr;
+  hipStream_t s = nullptr;
+  int cur = 0;
+};
+
+gmm_status batch_pass(BatchRun &r, int mode, int umode, double reg,
+                      double *loglik, int ll_stride, int ll_index,
+                      float *out_w = nullptr, float *out_mu = nullptr,
+                      float *out_cov = nullptr) {
+  const BatchPlan &bp = *r.bp;
+  unsigned char *plan = at<unsigned char>(r.ws, bp.plan);
+  const BFrame *frames = reinterpret_cast<const BFrame *>(plan);
+  for (const auto &c : bp.classes) {
+    c.launch(c, r.s, at<float4>(r.ws, bp.pts4), at<float>(r.ws, bp.cpar[r.cur]),
+             at<float4>(r.ws, bp.shift[r.cur]), at<double>(r.ws, bp.part), frames,
+             reinterpret_cast<const BSeg *>(plan + c.seg_off),
+             reinterpret_cast<const int *>(plan + c.blk_off), mode);
+    HIP_TRY(hipGetLastError());
+  }
+  const int only_L = mode == kSoftLogLik;
+  const int ncx = (only_L ? 1 : (bp.ncols_max + 63) / 64);
+  hipLaunchKernelGGL(reduce_frames_kernel, dim3(bp.B, ncx), dim3(256), 0, r.s,
+                     at<double>(r.ws, bp.part), frames, only_L,
+                     at<double>(r.ws, bp.red));
+  HIP_TRY(hipGetLastError());
+  const int nxt = 1 - r.cur;
+  const size_t lds = ((size_t)bp.ncols_max + kUpdThreads + 2 * (size_t)bp.Kmax) * sizeof(double);
+  hipLaunchKernelGGL(update_frames_kernel, dim3(bp.B), dim3(kUpdThreads), lds,
+                     r.s, at<double>(r.ws, bp.red), frames, mode, umode, reg,
+                     at<float>(r.ws, bp.cpar[r.cur]), at<float4>(r.ws, bp.shift[r.cur]),
+                     at<float>(r.ws, bp.cpar[nxt]), at<float4>(r.ws, bp.shift[nxt]),
+                     at<double>(r.ws, bp.th64), loglik, ll_stride, ll_index,
+                     out_w, out_mu, out_cov, at<uint32_t>(r.ws, bp.status));
+  HIP_TRY(hipGetLastError());
+  if (umode != kUpdNone) r.cur = nxt;
+  return GMM_OK;
+}
+
+gmm_status enqueue_batched(BatchRun &r, const int32_t *labels, float *w,
+                           float *mu, float *cov, double *loglik,
+                           const gmm_fit_opts *opts) {
+  gmm_status st;
+  const int T = opts->iters, ll = T + 1;
+  const double reg = opts->reg_covar;
+  const BatchPlan &bp = *r.bp;
+  const BFrame *frames = reinterpret_cast<const BFrame *>(at<unsigned char>(r.ws, bp.plan));
+  if (labels) {
+    if ((st = batch_pass(r, kLabels, kUpdMeanOnly, reg, nullptr, ll, 0)) != GMM_OK) return st;
+    if ((st = batch_pass(r, kLabels, kUpdFull, reg, nullptr, ll, 0)) != GMM_OK) return st;
+  } else {
+    hipLaunchKernelGGL(precompute_frames_kernel, dim3(bp.B), dim3(kPreThreads), 0,
+                       r.s, w, mu, cov, frames, at<float>(r.ws, bp.cpar[r.cur]),
+                       at<float4>(r.ws, bp.shift[r.cur]), at<double>(r.ws, bp.th64),
+                       at<uint32_t>(r.ws, bp.status));
+    HIP_TRY(hipGetLastError());
+  }
+  for (int t = 0; t < T; ++t) {
+    if (opts->moment_mode == GMM_MOMENTS_TWO_PASS) {
+      if ((st = batch_pass(r, kSoftStats, kUpdMeanOnly, reg, loglik, ll, t)) != GMM_OK) return st;
+      if ((st = batch_pass(r, kSoftStats, kUpdFull, reg, nullptr, ll, t)) != GMM_OK) return st;
+    } else {
+      if ((st = batch_pass(r, kSoftStats, kUpdFull, reg, loglik, ll, t)) != GMM_OK) return st;
+    }
+  }
+  return batch_pass(r, kSoftLogLik, kUpdNone, reg, loglik, ll, T, w, mu, cov);
 }
 
 }  // namespace
@@ -637,9 +883,11 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
   r.ws = ws;
   const bool sync = !(opts->flags & GMM_FLAG_ASYNC);
 
-  if (graphs_enabled() && !guard.ptr) {
+  // Profiled calls launch directly: the HIP runtime does not time events
+  // that a captured graph records.
+  if (graphs_enabled() && !guard.ptr && !g_prof.on) {
     FitKey key{pts, init_labels, w, mu, cov, loglik, ws, n, ws_bytes,
-               opts->reg_covar, k, opts->iters, opts->moment_mode, 0, g_prof.on};
+               opts->reg_covar, k, opts->iters, opts->moment_mode, 0};
     (void)hipGetDevice(&key.dev);
     std::lock_guard<std::mutex> lk(g_graph_mu);
     bool found = false;
@@ -650,7 +898,6 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
       if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
         Run rc = r;
         rc.s = cs;
-        rc.sink = g_prof.on ? &e->pairs : nullptr;
         gmm_status cst = enqueue_fit(rc, pts, n, init_labels, w, mu, cov, loglik, opts);
         hipGraph_t g = nullptr;
         hipError_t ee = hipStreamEndCapture(cs, &g);
@@ -658,18 +905,12 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
             hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0) != hipSuccess)
           e->exec = nullptr;
         if (g) (void)hipGraphDestroy(g);
-        if (!e->exec) destroy_pairs(e->pairs);
       }
       (void)hipGetLastError();
     }
     if (e->exec) {
       HIP_TRY(hipGraphLaunch(e->exec, r.s));
-      st = finish(r, sync || g_prof.on);
-      if (g_prof.on) {
-        hipError_t pe = add_elapsed(e->pairs);
-        if (pe != hipSuccess) return fail(GMM_ERR_DEVICE, "profiling: %s", hipGetErrorString(pe));
-      }
-      return st;
+      return finish(r, sync);
     }
   }
   r.sink = g_prof.on ? &g_prof.pending : nullptr;
@@ -713,6 +954,107 @@ gmm_status gmm_loglik(const float *pts, int64_t n, const float *pose6,
   if ((st = stage(r, pts, n, nullptr, Rt)) != GMM_OK) return st;
   if ((st = run_precompute(r, w, mu, cov)) != GMM_OK) return st;
   return run_pass(r, kSoftLogLik, kUpdNone, 0.0, out_L, out_lse);
+}
+
+
+size_t gmm_fit_batched_workspace_size(int32_t B, const int64_t *pt_off,
+                                      const int32_t *k_off,
+                                      const gmm_fit_opts *opts) {
+  (void)opts;
+  g_err[0] = 0;
+  if (!pt_off || !k_off) return 0;
+  BatchPlan bp;
+  if (make_batch_plan(B, pt_off, k_off, &bp) != GMM_OK) return 0;
+  return bp.total;
+}
+
+gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
+                           const int32_t *k_off, const int32_t *init_labels,
+                           float *w, float *mu, float *cov, double *loglik,
+                           const gmm_fit_opts *opts, void *ws, size_t ws_bytes,
+                           void *stream) {
+  g_err[0] = 0;
+  if (!pts || !pt_off || !k_off || !w || !mu || !cov || !opts)
+    return fail(GMM_ERR_INVALID_ARG, "NULL pointer argument");
+  if (opts->iters < 0) return fail(GMM_ERR_INVALID_ARG, "iters < 0");
+  if (!(opts->reg_covar >= 0.0) || !isfinite(opts->reg_covar))
+    return fail(GMM_ERR_INVALID_ARG, "reg_covar must be finite and >= 0");
+  if (opts->moment_mode != GMM_MOMENTS_SHIFTED &&
+      opts->moment_mode != GMM_MOMENTS_TWO_PASS)
+    return fail(GMM_ERR_INVALID_ARG, "unknown moment_mode");
+  if (opts->flags & ~GMM_FLAG_ASYNC) return fail(GMM_ERR_INVALID_ARG, "unknown flags");
+  if (pt_off[0] != 0 || k_off[0] != 0)
+    return fail(GMM_ERR_INVALID_ARG, "offsets must start at 0");
+  BatchPlan bp;
+  gmm_status st = make_batch_plan(B, pt_off, k_off, &bp);
+  if (st != GMM_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  WsGuard guard;
+  if ((st = get_ws(&ws, &ws_bytes, bp.total, s, &guard)) != GMM_OK) return st;
+  // upload the plan (host buffer kept alive until the copy has completed)
+  std::vector<unsigned char> host(bp.plan_bytes, 0);
+  memcpy(host.data(), bp.frames.data(), sizeof(BFrame) * B);
+  for (const auto &c : bp.classes) {
+    memcpy(host.data() + c.seg_off, c.segs.data(), sizeof(BSeg) * c.segs.size());
+    memcpy(host.data() + c.blk_off, c.blk.data(), sizeof(int) * c.blk.size());
+  }
+  HIP_TRY(hipMemcpyAsync(at<unsigned char>(ws, bp.plan), host.data(),
+                         bp.plan_bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  hipLaunchKernelGGL(init_kernel, dim3(64), dim3(256), 0, s,
+                     at<uint32_t>(ws, bp.status), nullptr, 0,
+                     init_labels ? at<float4>(ws, bp.shift[0]) : nullptr, bp.Ktot);
+  HIP_TRY(hipGetLastError());
+  // stage every frame into its tiles
+  for (int f = 0; f < B; ++f) {
+    const int64_t n = pt_off[f + 1] - pt_off[f];
+    const int64_t npad = ((n + kBatchT - 1) / kBatchT) * kBatchT;
+    hipLaunchKernelGGL(stage_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256),
+                       0, s, pts + 3 * pt_off[f], n, npad,
+                       init_labels ? init_labels + pt_off[f] : nullptr,
+                       bp.frames[f].K, nullptr,
+                       at<float4>(ws, bp.pts4) + bp.frames[f].toff * kBatchT,
+                       at<uint32_t>(ws, bp.status));
+    HIP_TRY(hipGetLastError());
+  }
+  BatchRun r;
+  r.bp = &bp;
+  r.ws = ws;
+  r.s = s;
+  // the iteration loop as one graph (direct launches when capture fails)
+  bool done = false;
+  if (graphs_enabled()) {
+    hipStream_t cs = capture_stream();
+    hipEvent_t ev = nullptr;
+    if (cs && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+        hipEventRecord(ev, s) == hipSuccess && hipStreamWaitEvent(cs, ev, 0) == hipSuccess &&
+        hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      BatchRun rc = r;
+      rc.s = cs;
+      gmm_status cst = enqueue_batched(rc, init_labels, w, mu, cov, loglik, opts);
+      hipGraph_t g = nullptr;
+      hipError_t ee = hipStreamEndCapture(cs, &g);
+      hipGraphExec_t exec = nullptr;
+      if (cst == GMM_OK && ee == hipSuccess && g &&
+          hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess) {
+        hipError_t le = hipGraphLaunch(exec, s);
+        done = le == hipSuccess;
+        if (done) HIP_TRY(hipStreamSynchronize(s));
+        (void)hipGraphExecDestroy(exec);
+      }
+      if (g) (void)hipGraphDestroy(g);
+    }
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipGetLastError();
+  }
+  if (!done && (st = enqueue_batched(r, init_labels, w, mu, cov, loglik, opts)) != GMM_OK)
+    return st;
+  if (opts->flags & GMM_FLAG_ASYNC) return GMM_OK;
+  uint32_t bits = 0;
+  HIP_TRY(hipMemcpyAsync(&bits, at<uint32_t>(ws, bp.status), sizeof bits,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return status_from_bits(bits);
 }
 
 gmm_status gmm_profile_enable(int on) {

@@ -1,0 +1,133 @@
+"""GPU parity of gmm_fit_batched: every frame of a batched fit equals the
+FP64 oracle's fit of that frame (same bar as single fits: one step 1e-5,
+final log-likelihood 1e-4), and matches the per-frame gmm_fit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2307_00071_amd as gmm
+from paper_2307_00071_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _to(x, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(DEV, dtype)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) /
+                 max(np.linalg.norm(b), 1e-300))
+
+
+def _frames(count, seed, nmin, nmax, kmin, kmax):
+    rng = np.random.default_rng(seed)
+    out = []
+    for f in range(count):
+        X = synth.depth_frame(seed=seed + f)
+        n = int(rng.integers(nmin, nmax + 1))
+        k = int(rng.integers(kmin, kmax + 1))
+        idx = np.sort(rng.choice(X.shape[0], n, replace=False))
+        out.append((np.ascontiguousarray(X[idx]), k))
+    return out
+
+
+def test_batched_matches_oracle_per_frame():
+    print("case: batched 6 frames", flush=True)
+    frames = _frames(6, 500, 3000, 12000, 1, 150)
+    frames.append((synth.gaussian_blobs(1, n_per=400)[0], 8))
+    labs = [synth.kmeanspp_labels(X, k, 3) for X, k in frames]
+    T = 12
+    res = gmm.fit_batched([_to(X) for X, _ in frames], [k for _, k in frames],
+                          iters=T, labels_list=[_to(l, torch.int32) for l in labs])
+    torch.cuda.synchronize()
+    for (X, k), lab, r in zip(frames, labs, res):
+        w, mu, cov, Lr = oracle.fit(X, k, 1e-3, T, labels=lab)
+        L = r.loglik.cpu().numpy()
+        err = np.abs(L - Lr) / np.maximum(np.abs(Lr), X.shape[0])
+        print(k, X.shape[0], err.max(), flush=True)
+        assert err.max() <= 1e-4
+        assert _rel(r.means.cpu().numpy(), mu) <= 1e-4
+
+
+def test_batched_blocks_spanning_several_frames():
+    """More tiles than resident blocks in one M-phase class, so blocks walk
+    several frame segments; K in [65, 102] puts every frame in the class
+    whose last point subset reads the zero pad column of the LDS rows."""
+    print("case: batched multi-segment blocks", flush=True)
+    rng = np.random.default_rng(42)
+    frames = []
+    for f in range(24):
+        X = synth.depth_frame(seed=1200 + f)
+        n = int(rng.integers(9000, 14000))
+        idx = np.sort(rng.choice(X.shape[0], n, replace=False))
+        frames.append((np.ascontiguousarray(X[idx]), int(rng.integers(65, 103))))
+    labs = [synth.kmeanspp_labels(X, k, 3) for X, k in frames]
+    T = 4
+    res = gmm.fit_batched([_to(X) for X, _ in frames], [k for _, k in frames],
+                          iters=T, labels_list=[_to(l, torch.int32) for l in labs])
+    torch.cuda.synchronize()
+    for (X, k), lab, r in zip(frames, labs, res):
+        w, mu, cov, Lr = oracle.fit(X, k, 1e-3, T, labels=lab)
+        L = r.loglik.cpu().numpy()
+        err = np.abs(L - Lr) / np.maximum(np.abs(Lr), X.shape[0])
+        assert err.max() <= 1e-4, (k, err.max())
+        assert _rel(r.means.cpu().numpy(), mu) <= 1e-4
+
+
+def test_batched_one_step_and_two_pass():
+    print("case: batched one step", flush=True)
+    frames = _frames(4, 700, 2000, 9000, 5, 120)
+    thetas = []
+    for X, k in frames:
+        lab = synth.kmeanspp_labels(X, k, 4)
+        w, mu, cov, _ = oracle.fit(X, k, 1e-3, 2, labels=lab)
+        thetas.append(tuple(a.astype(np.float32) for a in (w, mu, cov)))
+    for mode in ("shifted", "two_pass"):
+        res = gmm.fit_batched([_to(X) for X, _ in frames], [k for _, k in frames],
+                              iters=1, theta0_list=[tuple(_to(a) for a in t) for t in thetas],
+                              moment_mode=mode)
+        torch.cuda.synchronize()
+        for (X, k), th, r in zip(frames, thetas, res):
+            wr, mur, covr, L0 = oracle.em_step(X, *(a.astype(np.float64) for a in th), 1e-3)
+            assert _rel(r.weights.cpu().numpy(), wr) <= 1e-5
+            assert _rel(r.means.cpu().numpy(), mur) <= 1e-5
+            assert _rel(r.covariances.cpu().numpy(), covr) <= 1e-5
+            assert abs(r.loglik[0].item() - L0) <= 1e-5 * max(abs(L0), X.shape[0])
+
+
+def test_batched_equals_single_fits():
+    """Same E-step/M-step per frame: batched and single fits agree to FP32
+    summation-order rounding (different tile partitions)."""
+    print("case: batched vs single", flush=True)
+    frames = _frames(5, 900, 5000, 30000, 10, 200)
+    labs = [synth.kmeanspp_labels(X, k, 5) for X, k in frames]
+    T = 20
+    res = gmm.fit_batched([_to(X) for X, _ in frames], [k for _, k in frames],
+                          iters=T, labels_list=[_to(l, torch.int32) for l in labs])
+    for (X, k), lab, r in zip(frames, labs, res):
+        s = gmm.fit(_to(X), k, iters=T, labels=_to(lab, torch.int32))
+        Lb, Ls = r.loglik.cpu().numpy(), s.loglik.cpu().numpy()
+        assert np.abs(Lb - Ls).max() <= 1e-6 * np.abs(Ls).max()
+
+
+def test_batched_deterministic_and_errors():
+    print("case: batched determinism", flush=True)
+    frames = _frames(3, 1100, 1000, 5000, 3, 60)
+    labs = [synth.kmeanspp_labels(X, k, 6) for X, k in frames]
+    args = ([_to(X) for X, _ in frames], [k for _, k in frames])
+    a = gmm.fit_batched(*args, iters=5, labels_list=[_to(l, torch.int32) for l in labs])
+    b = gmm.fit_batched(*args, iters=5, labels_list=[_to(l, torch.int32) for l in labs])
+    for ra, rb in zip(a, b):
+        for u, v in zip(ra, rb):
+            np.testing.assert_array_equal(u.cpu().numpy(), v.cpu().numpy())
+    from paper_2307_00071_amd import _lib
+    bad = [l.copy() for l in labs]
+    bad[1][7] = frames[1][1]        # label == K_f: out of range
+    with pytest.raises(_lib.GmmError):
+        gmm.fit_batched(*args, iters=2, labels_list=[_to(l, torch.int32) for l in bad])
+    with pytest.raises(_lib.GmmError):
+        gmm.fit_batched(*args[:1], [600, 3, 3], iters=1,
+                        labels_list=[_to(l, torch.int32) for l in labs])
