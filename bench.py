@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-iters", type=int, default=20)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 256 MiB device-to-device tensor copy "
+                         "(a known-size reference for memory counters)")
     return ap.parse_args()
 
 
@@ -136,6 +139,12 @@ def main():
     from paper_2307_00071_amd import _lib, synth
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     K, T = args.k, args.iters
     X = synth.depth_frame(0)
     lab = synth.kmeanspp_labels(X, K, 1)

@@ -181,6 +181,19 @@ gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
                            const gmm_fit_opts *opts, void *ws, size_t ws_bytes,
                            void *stream);
 
+/* ------------------------------------------------------------ autotuning
+ * With autotuning on (gmm_set_autotune(1), or GMM_AUTOTUNE=1 in the
+ * environment), the first gmm_fit for a new (device arch, K, N bucket =
+ * floor(log2 N)) times every tile shape the library can run on one E+M pass
+ * of the caller's own data (the parameters are not changed by it), keeps
+ * the fastest for this process and, when GMM_AUTOTUNE_CACHE names a file,
+ * appends "arch K bucket shape" lines to it and reads it back next time.
+ * GMM_TILE_SHAPE=<name> in the environment forces one shape when it can
+ * run the given K.  gmm_tile_config returns the shape a call with (n, k)
+ * would use now (static string, "" on bad sizes). */
+gmm_status gmm_set_autotune(int on);
+const char *gmm_tile_config(int64_t n, int32_t k);
+
 /* ------------------------------------------------------------ profiling
  * Kernel timing for benchmarks.  While enabled (per calling host thread),
  * every E+M statistics launch of the tile kernel made by gmm_fit is

@@ -24,6 +24,7 @@ EXPORTS = (
     "gmm_loglik_workspace_size", "gmm_loglik",
     "gmm_loglik_backward_workspace_size", "gmm_loglik_backward",
     "gmm_fit_batched_workspace_size", "gmm_fit_batched",
+    "gmm_set_autotune", "gmm_tile_config",
     "gmm_profile_enable", "gmm_profile_read",
 )
 
@@ -81,6 +82,10 @@ def load():
         i32, vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
         vp, vp, vp, vp, vp, ctypes.POINTER(FitOpts), vp, sz, vp]
     lib.gmm_fit_batched.restype = ctypes.c_int
+    lib.gmm_set_autotune.argtypes = [ctypes.c_int]
+    lib.gmm_set_autotune.restype = ctypes.c_int
+    lib.gmm_tile_config.argtypes = [i64, i32]
+    lib.gmm_tile_config.restype = ctypes.c_char_p
     lib.gmm_profile_enable.argtypes = [ctypes.c_int]
     lib.gmm_profile_enable.restype = ctypes.c_int
     lib.gmm_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double),
@@ -107,3 +112,12 @@ def profile_read():
     n = ctypes.c_int64(0)
     check(load().gmm_profile_read(ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def set_autotune(on: bool) -> None:
+    check(load().gmm_set_autotune(1 if on else 0))
+
+
+def tile_config(n: int, k: int) -> str:
+    """Name of the tile shape a fit of n points, k components uses now."""
+    return load().gmm_tile_config(int(n), int(k)).decode()

@@ -85,9 +85,9 @@ __device__ inline bool chol3(const double *C, double *L) {
 // P = L^-1 (lower) by forward substitution, same packed order.
 __device__ inline void tri_inv3(const double *L, double *P) {
   double p00 = 1.0 / L[0], p11 = 1.0 / L[2], p22 = 1.0 / L[5];
-  double p10 = -L[1] * p00 / L[2];
-  double p21 = -L[4] * p11 / L[5];
-  double p20 = -(L[3] * p00 + L[4] * p10) / L[5];
+  double p10 = -L[1] * p00 * p11;
+  double p21 = -L[4] * p11 * p22;
+  double p20 = -(L[3] * p00 + L[4] * p10) * p22;
   P[0] = p00; P[1] = p10; P[2] = p11; P[3] = p20; P[4] = p21; P[5] = p22;
 }
 
@@ -113,8 +113,8 @@ __device__ inline double component_terms(int b, double pi, const double *mu,
     return -INFINITY;
   }
   tri_inv3(L, P);
-  const double logdiag = log(P[0]) + log(P[2]) + log(P[5]);
-  const double c = log(pi) - 1.5 * kLn2Pi + logdiag;
+  // ln pi + sum_j ln P_jj = ln(pi P00 P11 P22), one logarithm
+  const double c = log(pi * P[0] * P[2] * P[5]) - 1.5 * kLn2Pi;
   const double s = sqrt(0.5 * kLog2e);
   for (int j = 0; j < 6; ++j) q[4 + j] = (float)(s * P[j]);
   return c * kLog2e;
@@ -163,6 +163,38 @@ __device__ inline void apply_bound(int K, const double *sC, float *cpar,
   if (threadIdx.x == 0) *reinterpret_cast<double *>(cpar + (size_t)K * kParStride) = C;
 }
 
+// Block-wide reductions in a fixed order with two barriers: a butterfly in
+// each wave, then the wave results added in wave order by one thread.
+template <int NT>
+__device__ inline double block_sum_fast(double v, double *scratch) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = scratch[0];
+    for (int j = 1; j < NT / 64; ++j) t += scratch[j];
+    scratch[NT / 64] = t;
+  }
+  __syncthreads();
+  return scratch[NT / 64];
+}
+
+template <int NT>
+__device__ inline double block_max_fast(double v, double *scratch) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = scratch[0];
+    for (int j = 1; j < NT / 64; ++j) t = fmax(t, scratch[j]);
+    scratch[NT / 64] = t;
+  }
+  __syncthreads();
+  return scratch[NT / 64];
+}
+
 // ------------------------------------------------------------------ M-step
 // From the reduced statistics tot[] (column s*K + b: N0, S1 (3), S2 (6); the
 // log-likelihood at 10 K) and the shift m the tile kernel subtracted:
@@ -170,16 +202,17 @@ __device__ inline void apply_bound(int K, const double *sC, float *cpar,
 //   Sigma = (S2 - S1 delta^T - delta S1^T + N0 delta delta^T) / N_b + lambda I
 // which is sum g (x - mu)(x - mu)^T / N_b + lambda I exactly;
 //   pi_b = N_b / sum_a N_a, then the eq. 3 terms for the next E-step.
-// Runs in one block of NT threads; sN, sC are K-double LDS arrays.
+// One block of NT >= K threads, thread b owns component b (registers only);
+// scratch holds NT / 64 + 1 doubles.
 template <int NT>
 __device__ void em_update_block(const double *tot, int K, int umode, double reg,
                                 const float *cpar_in, const float4 *shift_in,
                                 float *cpar_out, float4 *shift_out,
-                                double *th64, double *sN, double *sC,
-                                double *scratch, uint32_t *status) {
-  const int tid = threadIdx.x;
+                                double *th64, double *scratch, uint32_t *status) {
+  const int b = threadIdx.x;
+  const bool act = b < K;
   if (umode == kUpdMeanOnly) {
-    for (int b = tid; b < K; b += NT) {
+    if (act) {
       const double N0 = tot[b];
       const float4 mf = shift_in[b];
       const double Nb = N0 + kEpsN;
@@ -196,50 +229,44 @@ __device__ void em_update_block(const double *tot, int K, int umode, double reg,
     }
     // the E-step block of the current parameters carries over
     const int nf = (K + 1) * kParStride;
-    for (int i = tid; i < nf; i += NT) cpar_out[i] = cpar_in[i];
+    for (int i = b; i < nf; i += NT) cpar_out[i] = cpar_in[i];
     return;
   }
   // umode == kUpdFull
   const int ij[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
-  double part = 0.0;
-  for (int b = tid; b < K; b += NT) {
+  double Nb = 0.0, mu[3] = {0.0, 0.0, 0.0}, C[6] = {0, 0, 0, 0, 0, 0};
+  if (act) {
     const double N0 = tot[b];
     const double S1[3] = {tot[1 * K + b], tot[2 * K + b], tot[3 * K + b]};
     const float4 mf = shift_in[b];
     const double m[3] = {mf.x, mf.y, mf.z};
-    const double Nb = N0 + kEpsN;
-    double mu[3], dl[3];
+    Nb = N0 + kEpsN;
+    const double rN = 1.0 / Nb;
+    double dl[3];
     for (int j = 0; j < 3; ++j) {
-      mu[j] = (S1[j] + N0 * m[j]) / Nb;
+      mu[j] = (S1[j] + N0 * m[j]) * rN;
       dl[j] = mu[j] - m[j];
     }
     bool fin = isfinite(N0) && isfinite(S1[0]) && isfinite(S1[1]) && isfinite(S1[2]);
-    double *t = th64 + (size_t)b * kTh64Stride;
     for (int j = 0; j < 6; ++j) {
       const int r = ij[j][0], c = ij[j][1];
       const double s2 = tot[(4 + j) * K + b];
       const double v = s2 - S1[r] * dl[c] - dl[r] * S1[c] + N0 * dl[r] * dl[c];
-      t[4 + j] = v / Nb + ((r == c) ? reg : 0.0);
+      C[j] = v * rN + ((r == c) ? reg : 0.0);
       fin = fin && isfinite(s2);
     }
     if (!fin) set_status(status, kStNonFinite);
-    for (int j = 0; j < 3; ++j) t[1 + j] = mu[j];
-    sN[b] = Nb;
-    part += Nb;
   }
-  // sum_a N_a in a fixed order: per-thread partials (fixed component
-  // stride) then the fixed tree
-  const double Ntot = block_sum<NT>(part, scratch);
-  for (int b = tid; b < K; b += NT) {
-    const double *t = th64 + (size_t)b * kTh64Stride;
-    const double mu[3] = {t[1], t[2], t[3]};
-    const double C[6] = {t[4], t[5], t[6], t[7], t[8], t[9]};
-    const double c = component_terms(b, sN[b] / Ntot, mu, C, sN[b], cpar_out,
-                                     shift_out, th64);
+  const double Ntot = block_sum_fast<NT>(Nb, scratch);
+  double c = -INFINITY;
+  if (act) {
+    c = component_terms(b, Nb / Ntot, mu, C, Nb, cpar_out, shift_out, th64);
     if (!isfinite(c)) set_status(status, kStNotSpd);
-    sC[b] = c;
   }
-  apply_bound<NT>(K, sC, cpar_out, scratch);
+  double Cmax = block_max_fast<NT>(c, scratch);
+  if (!isfinite(Cmax)) Cmax = 0.0;
+  if (act) cpar_out[(size_t)b * kParStride + 3] = isfinite(c) ? (float)(c - Cmax) : -INFINITY;
+  if (b == 0) *reinterpret_cast<double *>(cpar_out + (size_t)K * kParStride) = Cmax;
 }
 
 // Caller-supplied theta_0 (FP32 w, mu, cov) -> FP64 state and E-step block;
@@ -375,7 +402,9 @@ __global__ void init_kernel(uint32_t *status, unsigned *counters, int ncnt,
 template <int BLOCK, int T>
 struct TileShape {
   static constexpr int G = BLOCK / T;  // component groups in the E-phase
-  static constexpr int TS = T + 1;     // LDS row: T points + 1 zero pad (odd)
+  // LDS row: T points + zero pad (odd stride: conflict-free), long enough
+  // for every point-subset split the host may pick (P * TRIP <= TS)
+  static constexpr int TS = T + (T == 64 ? 1 : 3);
   static_assert(BLOCK % T == 0, "tile must divide the block");
   static_assert(T % 64 == 0, "a wave must hold one component group");
 };
@@ -396,6 +425,15 @@ __host__ __device__ constexpr size_t tile_lds_bytes(int K, int KC) {
   return tile_lds_bytes_e<BLOCK, T>(K, KC) + S::TS * sizeof(float4) +
          (size_t)S::G * T * sizeof(float) + T * sizeof(float) +
          (BLOCK / 64) * sizeof(double);
+}
+
+// Zero the pad columns [T, TS) of the first rows E rows and the pad
+// entries of Xs: the last point subset reads them with weight 0.
+template <int TS, int T, int BLOCK>
+__device__ __forceinline__ void zero_pad(float *E, float4 *Xs, int rows) {
+  constexpr int W = TS - T;
+  for (int i = threadIdx.x; i < rows * W; i += BLOCK) E[(i / W) * TS + T + i % W] = 0.0f;
+  if (threadIdx.x < W) Xs[T + threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // l'_pb of one component (eq. 3 in log2 units, relative to the bound).
@@ -441,8 +479,12 @@ struct TileArgs {
   int ntiles, K, KC, P, mode, ncols;
 };
 
+#ifndef GMM_TILE_WPE
+#define GMM_TILE_WPE 1
+#endif
 template <int BLOCK, int T, int NCH, int TRIP>
-__global__ __launch_bounds__(BLOCK) void em_tile_kernel(
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(GMM_TILE_WPE, 8))) void em_tile_kernel(
     const float4 *__restrict__ pts,    // staged (x, y, z, tag), ntiles * T
     const float *__restrict__ cpar,    // K x 16 floats, then the bound C
     const float4 *__restrict__ shift,  // K
@@ -483,9 +525,8 @@ __global__ __launch_bounds__(BLOCK) void em_tile_kernel(
     for (int j = 0; j < kNStat; ++j) acc[c][j] = 0.0;
   }
   double Lacc = 0.0;
-  // the zero pad column of E and pad entry of Xs (read by the last subset)
-  for (int b = tid; b < KC; b += BLOCK) E[b * TS + T] = 0.0f;
-  if (tid < TS - T) Xs[T + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+  // the zero pad columns of E and pad entries of Xs (read by the last subset)
+  zero_pad<TS, T, BLOCK>(E, Xs, KC);
 
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const float4 x = pts[(size_t)tile * T + p];
@@ -542,10 +583,10 @@ __global__ __launch_bounds__(BLOCK) void em_tile_kernel(
           }
           mref = m;
         }
-        Xs[p] = make_float4(x.x, x.y, x.z, valid ? 1.0f / st : 0.0f);
+        Xs[p] = make_float4(x.x, x.y, x.z, valid ? __builtin_amdgcn_rcpf(st) : 0.0f);
         Mp[p] = mref;
         if (valid) {
-          const double lse = (Cb + (double)mref + (double)log2f(st)) * kLn2;
+          const double lse = (Cb + (double)mref + (double)__builtin_amdgcn_logf(st)) * kLn2;
           Lacc += lse;
           if (lse_out) lse_out[(size_t)tile * T + p] = (float)lse;
         }
@@ -677,9 +718,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdPtrs q, UpdArgs 
   const int tid = threadIdx.x;
   const int K = a.K;
   double *tot = reinterpret_cast<double *>(smem);  // ncols
-  double *scratch = tot + a.ncols;                 // kUpdThreads
-  double *sN = scratch + kUpdThreads;              // K
-  double *sC = sN + K;                             // K
+  double *scratch = tot + a.ncols;                 // kUpdThreads / 64 + 1
   for (int c = a.col0 + tid; c < a.ncols; c += kUpdThreads) {
     double t = 0.0;
 #pragma unroll
@@ -694,8 +733,8 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdPtrs q, UpdArgs 
   }
   if (a.umode != kUpdNone) {
     em_update_block<kUpdThreads>(tot, K, a.umode, a.reg, q.cpar_in, q.shift_in,
-                                 q.cpar_out, q.shift_out, q.th64, sN, sC,
-                                 scratch, q.status);
+                                 q.cpar_out, q.shift_out, q.th64, scratch,
+                                 q.status);
   } else if (q.out_w) {
     for (int b = tid; b < K; b += kUpdThreads) {
       const double *t = q.th64 + (size_t)b * kTh64Stride;
@@ -713,7 +752,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdPtrs q, UpdArgs 
 }
 
 inline size_t update_lds_bytes(int K) {
-  return ((size_t)kNStat * K + 1 + kUpdThreads + 2 * (size_t)K) * sizeof(double);
+  return ((size_t)kNStat * K + 1 + kUpdThreads / 64 + 2) * sizeof(double);
 }
 
 
@@ -758,8 +797,7 @@ __global__ __launch_bounds__(BLOCK) void em_batch_kernel(
   const int tid = threadIdx.x;
   const int p = tid % T;
   const int g = __builtin_amdgcn_readfirstlane(tid / T);
-  for (int b = tid; b < kc_max; b += BLOCK) E[b * TS + T] = 0.0f;
-  if (tid < TS - T) Xs[T + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+  zero_pad<TS, T, BLOCK>(E, Xs, kc_max);
 
   const int s0 = blk_seg[blockIdx.x], s1 = blk_seg[blockIdx.x + 1];
   for (int si = s0; si < s1; ++si) {
@@ -821,8 +859,8 @@ __global__ __launch_bounds__(BLOCK) void em_batch_kernel(
             }
             mref = m;
           }
-          Xs[p] = make_float4(x.x, x.y, x.z, valid ? 1.0f / st : 0.0f);
-          if (valid) Lacc += (Cb + (double)mref + (double)log2f(st)) * kLn2;
+          Xs[p] = make_float4(x.x, x.y, x.z, valid ? __builtin_amdgcn_rcpf(st) : 0.0f);
+          if (valid) Lacc += (Cb + (double)mref + (double)__builtin_amdgcn_logf(st)) * kLn2;
         }
       } else {
         for (int b = b_lo; b < b_hi; ++b) E[b * TS + p] = (b == tag) ? 1.0f : 0.0f;
@@ -859,9 +897,9 @@ __global__ __launch_bounds__(BLOCK) void em_batch_kernel(
       row[kNStat * K] = sum;
     }
     __syncthreads();   // E, D and wL are reused by the next segment
-    // D overwrote the start of E: restore the zero pad column (the next
+    // D overwrote the start of E: restore the zero pad columns (the next
     // segment's first barrier orders these stores before any M-phase read)
-    for (int b = tid; b < kc_max; b += BLOCK) E[b * TS + T] = 0.0f;
+    zero_pad<TS, T, BLOCK>(E, Xs, kc_max);
   }
 }
 
@@ -914,9 +952,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_frames_kernel(
   const BFrame F = frames[blockIdx.x];
   const int K = F.K, tid = threadIdx.x;
   double *tot = reinterpret_cast<double *>(smem);   // ncols
-  double *scratch = tot + F.ncols;                  // kUpdThreads
-  double *sN = scratch + kUpdThreads;               // K
-  double *sC = sN + K;                              // K
+  double *scratch = tot + F.ncols;                  // kUpdThreads / 64 + 1
   const int col0 = (mode == kSoftLogLik) ? kNStat * K : 0;
   for (int c = col0 + tid; c < F.ncols; c += kUpdThreads) tot[c] = red[F.roff + c];
   __syncthreads();
@@ -929,8 +965,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_frames_kernel(
   if (umode != kUpdNone) {
     em_update_block<kUpdThreads>(tot, K, umode, reg, cpar_in + F.cpoff,
                                  shift_in + F.koff, cpar_out + F.cpoff,
-                                 shift_out + F.koff, t64, sN, sC, scratch,
-                                 status);
+                                 shift_out + F.koff, t64, scratch, status);
   } else if (out_w) {
     for (int b = tid; b < K; b += kUpdThreads) {
       const double *t = t64 + (size_t)b * kTh64Stride;
@@ -1030,8 +1065,7 @@ __global__ __launch_bounds__(BLOCK) void em_bwd_kernel(
 #pragma unroll
   for (int j = 0; j < kNStat; ++j) acc[j] = 0.0;
   double Lacc = 0.0, pg[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int b = tid; b < KC; b += BLOCK) E[b * TS + T] = 0.0f;
-  if (tid < TS - T) Xs[T + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+  zero_pad<TS, T, BLOCK>(E, Xs, KC);
 
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const float4 x = pts[(size_t)tile * T + p];

@@ -140,6 +140,12 @@ bool tile_instance(int trip, LaunchFn *fn, const void **kfn) {
     return true;
   if constexpr (NCH > 1) {
     switch (trip) { GMM_TRIP_CASE(32) GMM_TRIP_CASE(64) default: return false; }
+  } else if constexpr (T == 128) {
+    switch (trip) {
+      GMM_TRIP_CASE(4) GMM_TRIP_CASE(8) GMM_TRIP_CASE(13) GMM_TRIP_CASE(16)
+      GMM_TRIP_CASE(26) GMM_TRIP_CASE(32) GMM_TRIP_CASE(64)
+      default: return false;
+    }
   } else {
     switch (trip) {
       GMM_TRIP_CASE(1) GMM_TRIP_CASE(2) GMM_TRIP_CASE(4) GMM_TRIP_CASE(5)
@@ -154,9 +160,10 @@ bool tile_instance(int trip, LaunchFn *fn, const void **kfn) {
 // Largest P <= pmax whose ceil(T/P) consecutive points per subset fit the
 // T + 1 entries of an LDS row (so the last subset reads only the zero pad).
 int pick_subsets(int pmax, int T) {
+  const int TS = T + (T == 64 ? 1 : 3);   // TileShape<., T>::TS
   for (int P = std::min(pmax, T); P >= 1; --P) {
     int trip = (T + P - 1) / P;
-    if (P * trip <= T + 1) return P;
+    if (P * trip <= TS) return P;
   }
   return 1;
 }
@@ -270,12 +277,128 @@ bool reduce_kernel_ready(int K) {
                              (int)lds) == hipSuccess;
 }
 
+// Tile shapes the library can run; the heuristic order is the fallback
+// when a shape has not been tuned.  Candidate 0..kNumCand-1.
+using MakeCfg = bool (*)(int, int64_t, TileCfg *);
+constexpr int kNumCand = 6;
+const MakeCfg kCand[kNumCand] = {
+    &make_cfg<512, 64, 1>,  &make_cfg<1024, 128, 1>, &make_cfg<512, 128, 1>,
+    &make_cfg<256, 64, 1>,  &make_cfg<1024, 64, 1>,  &make_cfg<1024, 64, 2>};
+const char *const kCandName[kNumCand] = {"b512t64", "b1024t128", "b512t128",
+                                         "b256t64", "b1024t64", "b1024t64c2"};
+
+int default_candidate(int K, int64_t n) {
+  TileCfg c;
+  if (K <= 128 && kCand[0](K, n, &c)) return 0;
+  if (kCand[4](K, n, &c)) return 4;
+  if (kCand[5](K, n, &c)) return 5;
+  return -1;
+}
+
+// ---- autotuner: per (device arch, K, N bucket) the fastest candidate by a
+// timed E+M pass on the caller's data at the first call; optional file cache
+// (GMM_AUTOTUNE_CACHE).  Enabled by gmm_set_autotune(1) or GMM_AUTOTUNE=1.
+struct TuneEntry {
+  int K = 0, nb = 0, dev = -1, cand = -1;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+int g_autotune = -1;   // -1: read the environment on first use
+bool g_tune_loaded = false;
+
+int n_bucket(int64_t n) {
+  int b = 0;
+  while ((int64_t)1 << (b + 1) <= n) ++b;
+  return b;
+}
+
+bool autotune_on() {
+  if (g_autotune < 0) {
+    const char *e = getenv("GMM_AUTOTUNE");
+    g_autotune = (e && e[0] == '1') ? 1 : 0;
+  }
+  return g_autotune == 1;
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *path = getenv("GMM_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE *f = fopen(path, "r");
+  if (!f) return;
+  char arch[64], name[64];
+  int K, nb;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t pr;
+  const bool have = hipGetDeviceProperties(&pr, dev) == hipSuccess;
+  while (fscanf(f, "%63s %d %d %63s", arch, &K, &nb, name) == 4) {
+    if (!have || strncmp(arch, pr.gcnArchName, strlen(arch)) != 0) continue;
+    for (int i = 0; i < kNumCand; ++i)
+      if (strcmp(name, kCandName[i]) == 0) g_tune.push_back(TuneEntry{K, nb, dev, i});
+  }
+  fclose(f);
+}
+
+int tuned_candidate(int K, int64_t n) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int nb = n_bucket(n);
+  for (const auto &e : g_tune)
+    if (e.K == K && e.nb == nb && e.dev == dev) return e.cand;
+  return -1;
+}
+
+void tune_store(int K, int64_t n, int cand) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  g_tune.push_back(TuneEntry{K, n_bucket(n), dev, cand});
+  const char *path = getenv("GMM_AUTOTUNE_CACHE");
+  hipDeviceProp_t pr;
+  if (path && hipGetDeviceProperties(&pr, dev) == hipSuccess) {
+    FILE *f = fopen(path, "a");
+    if (f) {
+      char arch[64];
+      snprintf(arch, sizeof arch, "%s", pr.gcnArchName);
+      char *colon = strchr(arch, ':');
+      if (colon) *colon = 0;
+      fprintf(f, "%s %d %d %s\n", arch, K, n_bucket(n), kCandName[cand]);
+      fclose(f);
+    }
+  }
+}
+
+// GMM_TILE_SHAPE=<name> forces one shape (when it can run this K).
+int forced_candidate() {
+  const char *e = getenv("GMM_TILE_SHAPE");
+  if (!e || !*e) return -1;
+  for (int i = 0; i < kNumCand; ++i)
+    if (strcmp(e, kCandName[i]) == 0) return i;
+  return -1;
+}
+
 bool pick_cfg(int K, int64_t n, TileCfg *out) {
   if (!reduce_kernel_ready(K)) return false;
-  if (K <= 128 && make_cfg<512, 64, 1>(K, n, out)) return true;
-  if (make_cfg<1024, 64, 1>(K, n, out)) return true;
-  if (make_cfg<1024, 64, 2>(K, n, out)) return true;
-  return false;
+  const int f = forced_candidate();
+  if (f >= 0 && kCand[f](K, n, out)) return true;
+  const int t = tuned_candidate(K, n);
+  if (t >= 0 && kCand[t](K, n, out)) return true;
+  const int d = default_candidate(K, n);
+  return d >= 0 && kCand[d](K, n, out);
+}
+
+// Largest grid over every runnable candidate: the workspace fits any of them.
+int max_grid(int K, int64_t n) {
+  int g = 0;
+  for (int i = 0; i < kNumCand; ++i) {
+    TileCfg c;
+    if (kCand[i](K, n, &c)) g = std::max(g, c.grid);
+  }
+  return g;
 }
 
 // Workspace layout: two parameter sets (a pass reads one and its epilogue
@@ -292,8 +415,8 @@ WsLayout ws_layout(int64_t n, int K, const TileCfg &c, int extra_cols = 0,
   WsLayout L{};
   size_t o = 0;
   L.ncols = kNStat * K + 1 + extra_cols;
-  L.nslots = std::max(c.grid, grid_override);
-  L.npad = ((n + c.tile - 1) / c.tile) * c.tile;
+  L.nslots = std::max(std::max(c.grid, grid_override), max_grid(K, n));
+  L.npad = ((n + 127) / 128) * 128;   // a multiple of every tile size
   L.status = o; o = align256(o + 256);
   L.counter = o; o = align256(o + sizeof(unsigned));
   L.pose64 = o; o = align256(o + 32 * sizeof(double));
@@ -367,6 +490,54 @@ struct Run {
   int cur = 0;   // parameter set the next pass reads
   std::vector<EventPair> *sink = nullptr;  // profiling pairs go here
 };
+
+// The tile kernel alone (writes the partial rows only).
+void launch_tiles(Run &r, const TileCfg &c, int mode, float *lse) {
+  const WsLayout &L = r.L;
+  TileArgs a;
+  a.ntiles = (int)(L.npad / c.tile);
+  a.K = r.K;
+  a.KC = c.KC;
+  a.P = c.P;
+  a.mode = mode;
+  a.ncols = L.ncols;
+  c.launch(c, r.s, at<float4>(r.ws, L.pts4), at<float>(r.ws, L.cpar[r.cur]),
+           at<float4>(r.ws, L.shift[r.cur]), at<double>(r.ws, L.part), lse, a);
+}
+
+// Autotuning: time every runnable tile shape on an E+M pass of the
+// current parameters (which no tile pass modifies) and keep the fastest.
+gmm_status autotune(Run &r, int64_t n) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = -1;
+  float best_ms = 0.0f;
+  TileCfg best_cfg;
+  for (int i = 0; i < kNumCand; ++i) {
+    TileCfg c;
+    if (!kCand[i](r.K, n, &c)) continue;
+    launch_tiles(r, c, kSoftStats, nullptr);   // warm-up
+    HIP_TRY(hipEventRecord(e0, r.s));
+    for (int rep = 0; rep < 3; ++rep) launch_tiles(r, c, kSoftStats, nullptr);
+    HIP_TRY(hipEventRecord(e1, r.s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (best < 0 || ms < best_ms) {
+      best = i;
+      best_ms = ms;
+      best_cfg = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best >= 0) {
+    tune_store(r.K, n, best);
+    r.c = best_cfg;
+  }
+  return GMM_OK;
+}
 
 // One pass: the tile kernel, then the reduction and the M-step update.
 gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot,
@@ -466,7 +637,8 @@ gmm_status finish(Run &r, bool sync) {
 // Every launch of one fit, in order.
 gmm_status enqueue_fit(Run &r, const float *pts, int64_t n,
                        const int32_t *init_labels, float *w, float *mu,
-                       float *cov, double *loglik, const gmm_fit_opts *opts) {
+                       float *cov, double *loglik, const gmm_fit_opts *opts,
+                       bool may_tune) {
   gmm_status st;
   if ((st = run_init(r, init_labels != nullptr)) != GMM_OK) return st;
   if ((st = stage(r, pts, n, init_labels, nullptr)) != GMM_OK) return st;
@@ -479,6 +651,10 @@ gmm_status enqueue_fit(Run &r, const float *pts, int64_t n,
   } else {
     if ((st = run_precompute(r, w, mu, cov)) != GMM_OK) return st;
   }
+  if (may_tune && autotune_on() && forced_candidate() < 0 &&
+      tuned_candidate(r.K, n) < 0 &&
+      (st = autotune(r, n)) != GMM_OK)
+    return st;
   for (int t = 0; t < opts->iters; ++t) {
     double *slot = loglik ? loglik + t : nullptr;
     if (opts->moment_mode == GMM_MOMENTS_TWO_PASS) {
@@ -898,7 +1074,7 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
       if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
         Run rc = r;
         rc.s = cs;
-        gmm_status cst = enqueue_fit(rc, pts, n, init_labels, w, mu, cov, loglik, opts);
+        gmm_status cst = enqueue_fit(rc, pts, n, init_labels, w, mu, cov, loglik, opts, false);
         hipGraph_t g = nullptr;
         hipError_t ee = hipStreamEndCapture(cs, &g);
         if (cst == GMM_OK && ee == hipSuccess && g &&
@@ -914,7 +1090,7 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
     }
   }
   r.sink = g_prof.on ? &g_prof.pending : nullptr;
-  if ((st = enqueue_fit(r, pts, n, init_labels, w, mu, cov, loglik, opts)) != GMM_OK) return st;
+  if ((st = enqueue_fit(r, pts, n, init_labels, w, mu, cov, loglik, opts, true)) != GMM_OK) return st;
   return finish(r, sync);
 }
 
@@ -1055,6 +1231,23 @@ gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
                          hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return status_from_bits(bits);
+}
+
+gmm_status gmm_set_autotune(int on) {
+  g_autotune = on ? 1 : 0;
+  return GMM_OK;
+}
+
+const char *gmm_tile_config(int64_t n, int32_t k) {
+  g_err[0] = 0;
+  if (check_sizes(n, k, false) != GMM_OK) return "";
+  TileCfg c;
+  const int f = forced_candidate();
+  if (f >= 0 && kCand[f](k, n, &c)) return kCandName[f];
+  const int t = tuned_candidate(k, n);
+  if (t >= 0 && kCand[t](k, n, &c)) return kCandName[t];
+  const int d = default_candidate(k, n);
+  return d >= 0 ? kCandName[d] : "";
 }
 
 gmm_status gmm_profile_enable(int on) {

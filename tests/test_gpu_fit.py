@@ -306,3 +306,39 @@ def test_graph_replay_matches_direct_launches():
     r = gmm.fit(pts, 32, iters=8, reg_covar=1e-3, labels=labt, workspace=ws)
     torch.cuda.synchronize()
     assert not np.array_equal(r.means.cpu().numpy(), outs[0][1])
+
+
+SHAPES = ["b512t64", "b1024t128", "b512t128", "b256t64", "b1024t64", "b1024t64c2"]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("K,n", [(100, 20011), (16, 5003), (200, 12000), (700, 9000)])
+def test_every_tile_shape_one_step_parity(shape, K, n, monkeypatch):
+    """Each tile shape the autotuner may pick meets the one-step bar."""
+    monkeypatch.setenv("GMM_TILE_SHAPE", shape)
+    if _lib.tile_config(n, K) != shape:
+        pytest.skip("shape %s cannot run K=%d" % (shape, K))
+    _case("shape %s K=%d n=%d" % (shape, K, n))
+    X = _depth_subset(n, seed=K + 3)
+    lab = synth.kmeanspp_labels(X, K, 2)
+    theta = oracle.fit(X, K, 1e-3, 2, labels=lab)[:3]
+    errs = _one_step(X, K, theta)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_autotune_picks_a_shape_and_keeps_parity(monkeypatch, tmp_path):
+    _case("autotune")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("GMM_AUTOTUNE_CACHE", str(cache))
+    _lib.set_autotune(True)
+    try:
+        X = _depth_subset(30011, seed=21)
+        lab = synth.kmeanspp_labels(X, 96, 2)
+        w, mu, cov, L = _fit(X, 96, 10, labels=lab)
+        shape = _lib.tile_config(X.shape[0], 96)
+        assert shape in SHAPES
+        assert cache.read_text().split()[-1] == shape
+        wr, mur, covr, Lr = oracle.fit(X, 96, 1e-3, 10, labels=lab)
+        assert np.abs(L - Lr).max() / max(np.abs(Lr).max(), X.shape[0]) <= 1e-4
+    finally:
+        _lib.set_autotune(False)
