@@ -342,3 +342,21 @@ def test_autotune_picks_a_shape_and_keeps_parity(monkeypatch, tmp_path):
         assert np.abs(L - Lr).max() / max(np.abs(Lr).max(), X.shape[0]) <= 1e-4
     finally:
         _lib.set_autotune(False)
+
+
+@pytest.mark.parametrize("K,n", [(100, 20011), (200, 9000), (700, 5000)])
+def test_poisoned_workspace_does_not_leak(K, n):
+    """A workspace full of NaN bytes (a reused buffer) gives the same fit as
+    a fresh one: nothing reads workspace memory it did not write."""
+    _case("poisoned workspace K=%d" % K)
+    X = _depth_subset(n, seed=K + 9)
+    lab = synth.kmeanspp_labels(X, K, 2)
+    ws = torch.full((gmm.fit_workspace_bytes(n, K, 3),), 0xFF, dtype=torch.uint8,
+                    device=DEV)
+    r = gmm.fit(_to(X), K, iters=3, reg_covar=1e-3, labels=_to(lab, torch.int32),
+                workspace=ws)
+    torch.cuda.synchronize()
+    wr, mur, covr, Lr = oracle.fit(X, K, 1e-3, 3, labels=lab)
+    L = r.loglik.cpu().numpy()
+    assert np.abs(L - Lr).max() / max(np.abs(Lr).max(), n) <= 1e-5
+    assert _rel(r.means.cpu().numpy(), mur) <= 1e-5
