@@ -13,10 +13,12 @@ Prints one JSON line:
   em_iters_per_s  T / (time per fit)
   roofline        the E+M tile kernel: algorithmic FLOP per launch
                   (42 FLOP per point-component evaluation) / its mean
-                  duration from HIP events recorded around every launch on
-                  the fit's stream, over a second timed region of the same
-                  fits with direct launches (HIP does not time events inside
-                  a replayed graph)
+                  duration from HIP events on the fit's stream, over a
+                  second timed region of the same fits with direct launches
+                  (HIP does not time events inside a replayed graph); each
+                  pair brackets 16 back-to-back launches of the same
+                  (idempotent) tile pass, so the pair's own dispatch latency
+                  is spread over 16 launches
   batched         64 uneven depth frames (N_f ~ U[20k, 300k], K_f ~ U[16,
                   200]) fitted by one gmm_fit_batched call vs 64 sequential
                   gmm_fit calls (direct launches), same T
@@ -39,6 +41,18 @@ METRIC = ("EM iters/s and point-component evals/s at N=307200,K=100; "
 FLOP_PER_EVAL = 42          # distance 19 + log-sum-exp 3 + statistics 20
 PEAK_FP32_VECTOR = 157.3    # TFLOP/s, MI355X FP32 vector (packed FMA rate)
 PEAK_FP32_NONPACKED = 78.6  # TFLOP/s, one FP32 FMA per lane per cycle
+PROFILE_REPS = 16           # tile launches per timed event pair
+
+# HBM traffic of one E+M tile launch at this workload, from two rocprofv3
+# --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, averaged over
+# the iteration launches), scaled by what the same counters read for a
+# 256 MiB device copy (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all
+# of them).  Valid only for the kernel source and tile shape it was taken
+# on: any other reports null.
+TRAFFIC = {"kernel_src_sha256": "d0701912365db466163a010b26c602ecb77dd063af69ec3bcca94f61635aee99",
+           "tile_shape": "b512t64", "N": 307200, "K": 100,
+           "fetch_kib": 2545.00, "fetch_factor": 2.0,
+           "write_kib": 6024.00, "write_factor": 1.0}
 
 
 def parse():
@@ -57,6 +71,22 @@ def parse():
                     help="first run one 256 MiB device-to-device tensor copy "
                          "(a known-size reference for memory counters)")
     return ap.parse_args()
+
+
+def tile_traffic_bytes(N, K):
+    """HBM bytes per tile launch from the recorded counters, or None when the
+    kernel source, tile shape or workload differs from where they were taken."""
+    import hashlib
+    from paper_2307_00071_amd import _lib
+    src = os.path.join(ROOT, "paper_2307_00071_amd", "csrc", "em_device.hpp")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    t = TRAFFIC
+    if (sha != t["kernel_src_sha256"] or (N, K) != (t["N"], t["K"])
+            or _lib.tile_config(N, K) != t["tile_shape"]):
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] +
+                     t["write_kib"] * t["write_factor"])
 
 
 def cpu_baseline(X, lab, K, T_hint, target_s):
@@ -168,14 +198,11 @@ def main():
     dt = time.perf_counter() - t0
     # second timed region: the same fits, direct launches, kernel events
     _lib.profile_read()
-    _lib.profile_enable(True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    _lib.profile_enable(PROFILE_REPS)
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
-    dt_direct = time.perf_counter() - t1
-    _lib.profile_enable(False)
+    _lib.profile_enable(0)
     tile_ms, launches = _lib.profile_read()
     L = r.loglik.cpu().numpy()
     assert np.all(np.isfinite(L)), "non-finite log-likelihood"
@@ -206,13 +233,13 @@ def main():
         "final_loglik": float(L[-1]),
         "roofline": {"bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_VECTOR, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                     "frac": achieved / PEAK_FP32_VECTOR,
+                     "traffic": tile_traffic_bytes(N, K),
                      "kernel": "em_tile_kernel (E-step + M-step statistics)",
                      "avg_launch_us": avg_s * 1e6, "launches": launches,
                      "peak_nonpacked": PEAK_FP32_NONPACKED,
                      "frac_nonpacked": achieved / PEAK_FP32_NONPACKED},
     }
-    out["ms_per_step_direct_launches"] = 1e3 * dt_direct / args.steps
     if not args.no_batched:
         out["batched"] = batched_vs_plain(args.batched_iters)
     if not args.no_cpu_baseline:

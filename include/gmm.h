@@ -195,14 +195,18 @@ gmm_status gmm_set_autotune(int on);
 const char *gmm_tile_config(int64_t n, int32_t k);
 
 /* ------------------------------------------------------------ profiling
- * Kernel timing for benchmarks.  While enabled (per calling host thread),
- * every E+M statistics launch of the tile kernel made by gmm_fit is
- * bracketed by two HIP events recorded on the caller's stream (such calls
- * launch their kernels directly instead of replaying a captured graph).
- * gmm_profile_read waits for the recorded events, returns the summed
- * kernel time (ms) and the launch count since the last read, and resets
- * them.  Errors: DEVICE when an event call fails. */
-gmm_status gmm_profile_enable(int on);
+ * Kernel timing for benchmarks.  While enabled (reps >= 1, per calling host
+ * thread), every E+M statistics pass of the tile kernel made by gmm_fit is
+ * launched reps times back to back between two HIP events recorded on the
+ * caller's stream (such calls launch their kernels directly instead of
+ * replaying a captured graph).  The tile kernel only reads the points and
+ * parameters and overwrites its own partial sums, so the repeats change no
+ * result; they spread the event pair's dispatch latency (a few
+ * microseconds) over reps launches.  reps = 0 disables; reps > 64 is
+ * INVALID_ARG.  gmm_profile_read waits for the recorded events, returns the
+ * summed elapsed time (ms) and the number of tile launches it covers since
+ * the last read, and resets both.  Errors: DEVICE when an event call fails. */
+gmm_status gmm_profile_enable(int reps);
 gmm_status gmm_profile_read(double *tile_ms_total, int64_t *tile_launches);
 
 #ifdef __cplusplus

@@ -102,8 +102,10 @@ def check(status: int) -> None:
         raise GmmError(status, detail)
 
 
-def profile_enable(on: bool) -> None:
-    check(load().gmm_profile_enable(1 if on else 0))
+def profile_enable(reps: int) -> None:
+    """reps >= 1: time each E+M tile pass of gmm_fit over reps back-to-back
+    launches between one event pair; 0: off."""
+    check(load().gmm_profile_enable(int(reps)))
 
 
 def profile_read():

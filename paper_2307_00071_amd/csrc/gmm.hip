@@ -48,11 +48,15 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // statistics launches wait in `pending` until gmm_profile_read.
 struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
+  int reps = 1;
 };
 
+// The events skip the system-scope release fence a default event adds at
+// its record: that fence writes back L2 and would be timed with the kernel.
 bool make_pair(EventPair *p) {
-  if (hipEventCreate(&p->a) != hipSuccess) return false;
-  if (hipEventCreate(&p->b) != hipSuccess) {
+  const unsigned fl = hipEventDisableSystemFence;
+  if (hipEventCreateWithFlags(&p->a, fl) != hipSuccess) return false;
+  if (hipEventCreateWithFlags(&p->b, fl) != hipSuccess) {
     (void)hipEventDestroy(p->a);
     return false;
   }
@@ -68,7 +72,7 @@ void destroy_pairs(std::vector<EventPair> &v) {
 }
 
 struct Profiler {
-  bool on = false;
+  int reps = 0;  // tile launches per timed pass; 0 = off
   double ms_total = 0.0;
   int64_t launches = 0;
   std::vector<EventPair> pending;
@@ -84,7 +88,7 @@ hipError_t add_elapsed(const std::vector<EventPair> &v) {
     e = hipEventElapsedTime(&ms, p.a, p.b);
     if (e != hipSuccess) return e;
     g_prof.ms_total += ms;
-    g_prof.launches += 1;
+    g_prof.launches += p.reps;
   }
   return hipSuccess;
 }
@@ -555,12 +559,15 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   const bool timed = r.sink && mode == kSoftStats;
   if (timed) {
     if (!make_pair(&pp)) return fail(GMM_ERR_DEVICE, "profiling event allocation failed");
+    pp.reps = g_prof.reps;
     r.sink->push_back(pp);
     HIP_TRY(hipEventRecord(pp.a, r.s));
   }
-  r.c.launch(r.c, r.s, at<float4>(r.ws, L.pts4), at<float>(r.ws, L.cpar[r.cur]),
-             at<float4>(r.ws, L.shift[r.cur]), at<double>(r.ws, L.part), lse, a);
-  HIP_TRY(hipGetLastError());
+  for (int rep = 0; rep < (timed ? g_prof.reps : 1); ++rep) {
+    r.c.launch(r.c, r.s, at<float4>(r.ws, L.pts4), at<float>(r.ws, L.cpar[r.cur]),
+               at<float4>(r.ws, L.shift[r.cur]), at<double>(r.ws, L.part), lse, a);
+    HIP_TRY(hipGetLastError());
+  }
   if (timed) HIP_TRY(hipEventRecord(pp.b, r.s));
   const int nxt = 1 - r.cur;
   const int col0 = (mode == kSoftLogLik) ? kNStat * r.K : 0;
@@ -1061,7 +1068,7 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
 
   // Profiled calls launch directly: the HIP runtime does not time events
   // that a captured graph records.
-  if (graphs_enabled() && !guard.ptr && !g_prof.on) {
+  if (graphs_enabled() && !guard.ptr && g_prof.reps == 0) {
     FitKey key{pts, init_labels, w, mu, cov, loglik, ws, n, ws_bytes,
                opts->reg_covar, k, opts->iters, opts->moment_mode, 0};
     (void)hipGetDevice(&key.dev);
@@ -1089,7 +1096,7 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
       return finish(r, sync);
     }
   }
-  r.sink = g_prof.on ? &g_prof.pending : nullptr;
+  r.sink = g_prof.reps > 0 ? &g_prof.pending : nullptr;
   if ((st = enqueue_fit(r, pts, n, init_labels, w, mu, cov, loglik, opts, true)) != GMM_OK) return st;
   return finish(r, sync);
 }
@@ -1250,8 +1257,11 @@ const char *gmm_tile_config(int64_t n, int32_t k) {
   return d >= 0 ? kCandName[d] : "";
 }
 
-gmm_status gmm_profile_enable(int on) {
-  g_prof.on = on != 0;
+gmm_status gmm_profile_enable(int reps) {
+  g_err[0] = 0;
+  if (reps < 0 || reps > 64)
+    return fail(GMM_ERR_INVALID_ARG, "profile repeats must be in [0, 64] (got %d)", reps);
+  g_prof.reps = reps;
   return GMM_OK;
 }
 

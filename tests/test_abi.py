@@ -51,6 +51,10 @@ def test_host_side_argument_errors(lib):
         assert lib.gmm_last_error().decode()
     st = lib.gmm_loglik(None, -3, None, 2, None, None, None, None, None, None, 0, None)
     assert st == 1
+    # profiling repeats outside [0, 64]; 0 (off) is accepted
+    assert lib.gmm_profile_enable(-1) == 1
+    assert lib.gmm_profile_enable(65) == 1
+    assert lib.gmm_profile_enable(0) == 0
     with pytest.raises(_lib.GmmError):
         _lib.check(1)
 
