@@ -204,6 +204,8 @@ def main():
     torch.cuda.synchronize()
     _lib.profile_enable(0)
     tile_ms, launches = _lib.profile_read()
+    pairs_eval, pairs_all = _lib.profile_pairs()
+    shape = _lib.tile_config(N, K)
     L = r.loglik.cpu().numpy()
     assert np.all(np.isfinite(L)), "non-finite log-likelihood"
 
@@ -235,10 +237,17 @@ def main():
                      "peak": PEAK_FP32_VECTOR, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR,
                      "traffic": tile_traffic_bytes(N, K),
-                     "kernel": "em_tile_kernel (E-step + M-step statistics)",
+                     "kernel": "%s (E-step + M-step statistics), shape %s"
+                               % ("em_cull_kernel" if shape.startswith("c")
+                                  else "em_tile_kernel", shape),
                      "avg_launch_us": avg_s * 1e6, "launches": launches,
                      "peak_nonpacked": PEAK_FP32_NONPACKED,
-                     "frac_nonpacked": achieved / PEAK_FP32_NONPACKED},
+                     "frac_nonpacked": achieved / PEAK_FP32_NONPACKED,
+                     # share of the N*K point-component pairs the kernel
+                     # computed (the rest were shown to be exactly zero)
+                     "evaluated_pair_fraction": pairs_eval / max(pairs_all, 1),
+                     "achieved_on_evaluated_pairs":
+                         achieved * pairs_eval / max(pairs_all, 1)},
     }
     if not args.no_batched:
         out["batched"] = batched_vs_plain(args.batched_iters)

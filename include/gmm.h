@@ -208,6 +208,12 @@ const char *gmm_tile_config(int64_t n, int32_t k);
  * the last read, and resets both.  Errors: DEVICE when an event call fails. */
 gmm_status gmm_profile_enable(int reps);
 gmm_status gmm_profile_read(double *tile_ms_total, int64_t *tile_launches);
+/* The (tile, component) pairs of the timed E+M launches since the last
+ * call: `all` = launches x tiles x K, `evaluated` = the pairs the kernels
+ * computed (all of them for a dense tile kernel; for the culled kernel,
+ * those its bound could not show to be exactly zero).  Waits for the
+ * device; resets both.  Errors: DEVICE. */
+gmm_status gmm_profile_pairs(int64_t *evaluated, int64_t *all);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,7 @@ EXPORTS = (
     "gmm_loglik_backward_workspace_size", "gmm_loglik_backward",
     "gmm_fit_batched_workspace_size", "gmm_fit_batched",
     "gmm_set_autotune", "gmm_tile_config",
-    "gmm_profile_enable", "gmm_profile_read",
+    "gmm_profile_enable", "gmm_profile_read", "gmm_profile_pairs",
 )
 
 
@@ -91,6 +91,9 @@ def load():
     lib.gmm_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int64)]
     lib.gmm_profile_read.restype = ctypes.c_int
+    lib.gmm_profile_pairs.argtypes = [ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.gmm_profile_pairs.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -114,6 +117,15 @@ def profile_read():
     n = ctypes.c_int64(0)
     check(load().gmm_profile_read(ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def profile_pairs():
+    """(evaluated, all) (tile, component) pairs of the timed E+M launches
+    since the last call."""
+    ev = ctypes.c_int64(0)
+    al = ctypes.c_int64(0)
+    check(load().gmm_profile_pairs(ctypes.byref(ev), ctypes.byref(al)))
+    return ev.value, al.value
 
 
 def set_autotune(on: bool) -> None:

@@ -50,6 +50,7 @@ enum UpdMode { kUpdFull = 0, kUpdMeanOnly = 1, kUpdNone = 2 };
 // ------------------------------------------------------------------ layout
 // E-step parameter block ("cpar"), per component (16 floats):
 //   [0..2] mu  [3] (c_b - C) * log2(e)  [4..9] s * P (P00 P10 P11 P20 P21 P22)
+//   [10] an upper bound of the Frobenius norm of s * P (tile culling)
 // with s = sqrt(log2(e) / 2), c_b = ln pi_b - 3/2 ln 2pi + sum_j ln P_jj
 // (eq. 3) and C = max_b c_b, so [3] - |P' (x - mu)|^2 = log2(e)(l_nb - C) <= 0.
 // After the K blocks: C * log2(e) as a double.
@@ -110,13 +111,20 @@ __device__ inline double component_terms(int b, double pi, const double *mu,
   double L[6], P[6];
   if (!chol3(C, L)) {
     for (int j = 0; j < 6; ++j) q[4 + j] = 0.0f;
+    q[10] = 0.0f;
     return -INFINITY;
   }
   tri_inv3(L, P);
   // ln pi + sum_j ln P_jj = ln(pi P00 P11 P22), one logarithm
   const double c = log(pi * P[0] * P[2] * P[5]) - 1.5 * kLn2Pi;
   const double s = sqrt(0.5 * kLog2e);
-  for (int j = 0; j < 6; ++j) q[4 + j] = (float)(s * P[j]);
+  double fro = 0.0;
+  for (int j = 0; j < 6; ++j) {
+    q[4 + j] = (float)(s * P[j]);
+    fro += P[j] * P[j];
+  }
+  // |P'|_F rounded up: the tile-culling bound needs an upper bound of |P'|_2
+  q[10] = (float)(s * sqrt(fro) * (1.0 + 1e-6));
   return c * kLog2e;
 }
 
@@ -477,6 +485,9 @@ __device__ __forceinline__ void mstep_run(const float *Eb, const float4 *Xb,
 // arguments so the parameter block is read with scalar loads).
 struct TileArgs {
   int ntiles, K, KC, P, mode, ncols;
+  // kernel timing only: the culled kernel adds the (tile, component) pairs
+  // it evaluated here; NULL otherwise
+  unsigned long long *pairs = nullptr;
 };
 
 #ifndef GMM_TILE_WPE
@@ -528,8 +539,13 @@ __attribute__((amdgpu_waves_per_eu(GMM_TILE_WPE, 8))) void em_tile_kernel(
   // the zero pad columns of E and pad entries of Xs (read by the last subset)
   zero_pad<TS, T, BLOCK>(E, Xs, KC);
 
+  // the next tile's point is loaded one tile ahead
+  float4 xn = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+  if ((int)blockIdx.x < a.ntiles) xn = pts[(size_t)blockIdx.x * T + p];
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    const float4 x = pts[(size_t)tile * T + p];
+    const float4 x = xn;
+    if (tile + (int)gridDim.x < a.ntiles)
+      xn = pts[(size_t)(tile + gridDim.x) * T + p];
     const int tag = __float_as_int(x.w);
     const bool valid = tag >= 0;
     if (mode != kLabels) {
@@ -657,6 +673,443 @@ __attribute__((amdgpu_waves_per_eu(GMM_TILE_WPE, 8))) void em_tile_kernel(
     row[kNStat * K] = sum;
   }
 
+}
+
+// ------------------------------------------------------ culled tile kernel
+//
+// Most tiles of a spatially ordered cloud lie far from most components:
+// for those pairs 2^l'_pb underflows to exactly 0 in FP32 for every point,
+// and the dense kernel spends its E- and M-work adding zeros.  The culled
+// kernel skips such pairs with a conservative bound.  With the tile's
+// bounding sphere (centre c, radius r) and P' = s P (|P'(x - mu)|^2 =
+// log2(e)/2 (x - mu)^T Sigma^-1 (x - mu)),
+//   |P'(x - mu)| >= |P'(c - mu)| - |P'|_F r   for every x in the sphere,
+// so l'_pb <= c'_b - max(0, |P'(c - mu)| - |P'|_F r)^2.  When that is below
+// kCullLog2 (2 units under the smallest FP32 subnormal exponent), e_pb
+// rounds to 0 for every point of the tile and the pair is skipped: the
+// result equals the dense kernel's up to the order of FP32 additions.
+//
+// A tile is T points (T / 64 point groups of one wave each).  Per tile:
+//  cull      wave w tests components 64w .. 64w + 63 (parameters held in
+//            registers for the whole launch) and stores the ballot; this is
+//            done one tile ahead, at the end of the previous tile;
+//  E-phase   the active components form an ordered list of slots; the
+//            waves of a point group take every R-th slot and store e_pb in
+//            LDS row `slot` (rows for SCAP slots; a tile with more active
+//            components recomputes the later rows chunk by chunk);
+//  normaliser  one thread per point: s_p, 1 / s_p, lse_p;
+//  M-phase   lanes = (slot, point subset of TRIP points), the P subsets of
+//            a slot in adjacent lanes: FP32 statistics, summed over the
+//            subsets with DPP in a fixed order and added to FP64
+//            per-component sums in LDS.
+// A point with s_p below 2^-100 (far from every component) is left out of
+// the M-phase and added afterwards, exactly as the dense kernel's fallback
+// does it: its own maximum over all K components, one lane per component.
+constexpr float kCullLog2 = -152.0f;
+
+template <int BLOCK, int T, int TRIP, int SCAP>
+struct CullShape {
+  static constexpr int NW = BLOCK / 64;  // waves
+  static constexpr int W = T / 64;       // point groups
+  static constexpr int R = NW / W;       // waves per point group (E-phase)
+  static constexpr int P = T / TRIP;     // point subsets per component
+  static constexpr int XS = T + P;       // Xs entries (one pad per subset)
+  static constexpr int RS = (T + P) | 1; // E row stride (odd)
+  static_assert(T % 64 == 0 && NW % W == 0 && R >= 1, "tile and block");
+  static_assert(P * TRIP == T && (P == 8 || P == 16), "subsets");
+};
+
+// LDS of the culled kernel for K components: E rows, Xs, shifts, the cull
+// parameters, FP64 sums, masks, fallback (max, sum) per point, wL, partial
+// normalisers, the active list and its length.
+template <int BLOCK, int T, int TRIP, int SCAP>
+__host__ __device__ constexpr size_t cull_lds_bytes(int K) {
+  using S = CullShape<BLOCK, T, TRIP, SCAP>;
+  return (((size_t)SCAP * S::RS * sizeof(float) + 15) & ~(size_t)15) +
+         (size_t)S::XS * sizeof(float4) + (size_t)K * sizeof(float4) +
+         (size_t)((K + 63) / 64) * 64 * 3 * sizeof(float4) +
+         (size_t)K * kNStat * sizeof(double) + 16 * sizeof(uint64_t) +
+         (size_t)S::W * sizeof(uint64_t) + (size_t)S::NW * sizeof(double) +
+         (size_t)T * sizeof(float2) + (size_t)S::R * T * sizeof(float) +
+         (size_t)K * sizeof(int) + 16;
+}
+
+// Bounding sphere of every tile of tpts staged points: (centre, radius),
+// radius < 0 for a tile of padding only.  One 256-thread block per tile.
+__global__ __launch_bounds__(256) void tile_sphere_kernel(
+    const float4 *__restrict__ pts, int tpts, float4 *__restrict__ sph) {
+  __shared__ float sh[4][6];
+  const int64_t t = blockIdx.x;
+  float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
+  float hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
+  for (int i = threadIdx.x; i < tpts; i += 256) {
+    const float4 x = pts[t * tpts + i];
+    if (__float_as_int(x.w) >= 0) {
+      lo0 = fminf(lo0, x.x); lo1 = fminf(lo1, x.y); lo2 = fminf(lo2, x.z);
+      hi0 = fmaxf(hi0, x.x); hi1 = fmaxf(hi1, x.y); hi2 = fmaxf(hi2, x.z);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo0 = fminf(lo0, __shfl_xor(lo0, off, 64));
+    lo1 = fminf(lo1, __shfl_xor(lo1, off, 64));
+    lo2 = fminf(lo2, __shfl_xor(lo2, off, 64));
+    hi0 = fmaxf(hi0, __shfl_xor(hi0, off, 64));
+    hi1 = fmaxf(hi1, __shfl_xor(hi1, off, 64));
+    hi2 = fmaxf(hi2, __shfl_xor(hi2, off, 64));
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[wv][0] = lo0; sh[wv][1] = lo1; sh[wv][2] = lo2;
+    sh[wv][3] = hi0; sh[wv][4] = hi1; sh[wv][5] = hi2;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int v = 1; v < 4; ++v) {
+    lo0 = fminf(lo0, sh[v][0]); lo1 = fminf(lo1, sh[v][1]); lo2 = fminf(lo2, sh[v][2]);
+    hi0 = fmaxf(hi0, sh[v][3]); hi1 = fmaxf(hi1, sh[v][4]); hi2 = fmaxf(hi2, sh[v][5]);
+  }
+  if (!(lo0 <= hi0)) {
+    sph[t] = make_float4(0.0f, 0.0f, 0.0f, -1.0f);
+    return;
+  }
+  const float c0 = 0.5f * (lo0 + hi0), c1 = 0.5f * (lo1 + hi1),
+              c2 = 0.5f * (lo2 + hi2);
+  const float e0 = hi0 - lo0, e1 = hi1 - lo1, e2 = hi2 - lo2;
+  // half diagonal, widened for the rounding of the centre and the norm
+  const float scale = fmaxf(fmaxf(fabsf(c0), fabsf(c1)), fabsf(c2)) + 1.0f;
+  const float r = 0.5f * sqrtf(e0 * e0 + e1 * e1 + e2 * e2) * (1.0f + 1e-5f) +
+                  1e-5f * scale;
+  sph[t] = make_float4(c0, c1, c2, r);
+}
+
+// v + the value of another lane (DPP, within rows of 16 lanes):
+// xor 1, xor 2 (quad_perm), lane 7 - l of the half row, lane 15 - l of the
+// row.  Applied in this order they sum 2, 4, 8 and 16 adjacent lanes.
+__device__ __forceinline__ float dpp_add_xor1(float v) {
+  return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_add_xor2(float v) {
+  return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_add_half_mirror(float v) {
+  return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_add_mirror(float v) {
+  return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, true));
+}
+
+// Sum of the 10 statistics over the P adjacent lanes of a slot.
+template <int P>
+__device__ __forceinline__ void subset_sum(float *a) {
+#pragma unroll
+  for (int j = 0; j < kNStat; ++j) {
+    a[j] = dpp_add_xor1(a[j]);
+    a[j] = dpp_add_xor2(a[j]);
+    a[j] = dpp_add_half_mirror(a[j]);
+    if (P == 16) a[j] = dpp_add_mirror(a[j]);
+  }
+}
+
+// Cull test of one tile sphere against this lane's component (parameters
+// in LDS: mu, c', P' (6), |P'|_F); the wave's ballot.
+__device__ __forceinline__ uint64_t cull_ballot(const float4 *cp, float4 sp) {
+  bool act = false;
+  if (sp.w >= 0.0f) {
+    const float4 u = cp[0], v = cp[1], z = cp[2];  // (mu, c'), (P'0..3), (P'4, P'5, |P'|)
+    const float d0 = sp.x - u.x, d1 = sp.y - u.y, d2 = sp.z - u.z;
+    const float z0 = v.x * d0;
+    const float z1 = fmaf(v.y, d0, v.z * d1);
+    const float z2 = fmaf(v.w, d0, fmaf(z.x, d1, z.y * d2));
+    const float dist = sqrtf(fmaf(z0, z0, fmaf(z1, z1, z2 * z2)));
+    const float bnd = fmaxf(dist - z.z * sp.w, 0.0f);
+    act = fmaf(-bnd, bnd, u.w) >= kCullLog2;
+  }
+  return __ballot(act);
+}
+
+#ifndef GMM_CULL_WPE
+#define GMM_CULL_WPE 1
+#endif
+template <int BLOCK, int T, int TRIP, int SCAP>
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
+    const float4 *__restrict__ pts,    // staged (x, y, z, tag), ntiles * T
+    const float4 *__restrict__ sph,    // ntiles bounding spheres
+    const float *__restrict__ cpar,    // K x 16 floats, then the bound C
+    const float4 *__restrict__ shift,  // K
+    double *__restrict__ part,         // grid rows of ncols
+    float *__restrict__ lse_out,       // N or NULL
+    TileArgs a) {
+  using S = CullShape<BLOCK, T, TRIP, SCAP>;
+  constexpr int NW = S::NW, W = S::W, R = S::R, P = S::P, RS = S::RS;
+  constexpr int SLOTS = BLOCK / P;  // slots per M round
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int K = a.K, mode = a.mode, ntiles = a.ntiles;
+  const int nchk = (K + 63) >> 6;
+  float *E = reinterpret_cast<float *>(smem);
+  float4 *Xs = reinterpret_cast<float4 *>(
+      smem + (((size_t)SCAP * RS * sizeof(float) + 15) & ~(size_t)15));
+  float4 *ShL = Xs + S::XS;
+  float4 *CP = ShL + K;                                    // [nchk * 64][3]
+  double *acc = reinterpret_cast<double *>(CP + (size_t)nchk * 64 * 3);
+  uint64_t *masks = reinterpret_cast<uint64_t *>(acc + (size_t)K * kNStat);  // [16]
+  uint64_t *fbmask = masks + 16;                                             // [W]
+  double *wL = reinterpret_cast<double *>(fbmask + W);
+  float2 *fbv = reinterpret_cast<float2 *>(wL + NW);
+  float *reds = reinterpret_cast<float *>(fbv + T);                          // [R][T]
+  int *list = reinterpret_cast<int *>(reds + R * T);
+  int *nact_s = list + K;
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int pg = w % W, rr = w / W;
+  const int t = pg * 64 + lane;     // this lane's point in a tile
+  const int tx = t + t / TRIP;      // its column in Xs and the E rows
+  const double Cb = *reinterpret_cast<const double *>(cpar + (size_t)K * kParStride);
+
+  for (int b = tid; b < K; b += BLOCK) {
+    ShL[b] = shift[b];
+    for (int j = 0; j < kNStat; ++j) acc[(size_t)b * kNStat + j] = 0.0;
+  }
+  for (int c = tid; c < nchk * 64; c += BLOCK) {
+    float4 u = make_float4(0.f, 0.f, 0.f, -INFINITY), v = make_float4(0.f, 0.f, 0.f, 0.f),
+           z = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (c < K) {
+      const float *q = cpar + (size_t)c * kParStride;
+      u = make_float4(q[0], q[1], q[2], q[3]);
+      v = make_float4(q[4], q[5], q[6], q[7]);
+      z = make_float4(q[8], q[9], q[10], 0.f);
+    }
+    CP[3 * c] = u;
+    CP[3 * c + 1] = v;
+    CP[3 * c + 2] = z;
+  }
+  double Lacc = 0.0;
+  unsigned long long npairs = 0;
+  const int grid = gridDim.x;
+  int tile = blockIdx.x;
+  __syncthreads();
+
+  // active list of a tile from the masks: wave w < nchk places chunk w
+  auto build_list = [&]() {
+    if (w < nchk) {
+      int off = 0;
+      for (int c = 0; c < w; ++c) off += __popcll(masks[c]);
+      const uint64_t m = masks[w];
+      const unsigned below = __builtin_amdgcn_mbcnt_hi(
+          (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+      if ((m >> lane) & 1ull) list[off + (int)below] = (w << 6) + lane;
+      if (w == nchk - 1 && lane == 0) *nact_s = off + __popcll(m);
+    }
+  };
+
+  // first tile: masks, list; the point and sphere of the next tile ahead
+  float4 xn = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+  float4 spn = make_float4(0.f, 0.f, 0.f, -1.0f);
+  if (tile < ntiles) {
+    xn = pts[(size_t)tile * T + t];
+    if (w < nchk) {
+      const uint64_t m = cull_ballot(CP + 3 * ((w << 6) + lane), sph[tile]);
+      if (lane == 0) masks[w] = m;
+    }
+    if (tile + grid < ntiles) spn = sph[tile + grid];
+  }
+  __syncthreads();
+  if (tile < ntiles) build_list();
+  __syncthreads();
+
+  for (; tile < ntiles; tile += grid) {
+    const float4 x = xn;
+    if (tile + grid < ntiles) xn = pts[(size_t)(tile + grid) * T + t];
+    const bool valid = __float_as_int(x.w) >= 0;
+    const int nact = *nact_s;
+
+    // ---- E-phase: slots rr, rr + R, ... of the active list, four at a time
+    float s = 0.0f;
+    {
+      int sl = rr;
+      for (; sl + 3 * R < nact; sl += 4 * R) {
+        const int b0 = __builtin_amdgcn_readfirstlane(list[sl]);
+        const int b1 = __builtin_amdgcn_readfirstlane(list[sl + R]);
+        const int b2 = __builtin_amdgcn_readfirstlane(list[sl + 2 * R]);
+        const int b3 = __builtin_amdgcn_readfirstlane(list[sl + 3 * R]);
+        const float e0 = __builtin_amdgcn_exp2f(
+            comp_logterm(cpar + (size_t)b0 * kParStride, x.x, x.y, x.z));
+        const float e1 = __builtin_amdgcn_exp2f(
+            comp_logterm(cpar + (size_t)b1 * kParStride, x.x, x.y, x.z));
+        const float e2 = __builtin_amdgcn_exp2f(
+            comp_logterm(cpar + (size_t)b2 * kParStride, x.x, x.y, x.z));
+        const float e3 = __builtin_amdgcn_exp2f(
+            comp_logterm(cpar + (size_t)b3 * kParStride, x.x, x.y, x.z));
+        s += e0; s += e1; s += e2; s += e3;
+        if (sl + 3 * R < SCAP) {
+          E[sl * RS + tx] = e0;
+          E[(sl + R) * RS + tx] = e1;
+          E[(sl + 2 * R) * RS + tx] = e2;
+          E[(sl + 3 * R) * RS + tx] = e3;
+        } else {
+          if (sl < SCAP) E[sl * RS + tx] = e0;
+          if (sl + R < SCAP) E[(sl + R) * RS + tx] = e1;
+          if (sl + 2 * R < SCAP) E[(sl + 2 * R) * RS + tx] = e2;
+        }
+      }
+      for (; sl < nact; sl += R) {
+        const int b0 = __builtin_amdgcn_readfirstlane(list[sl]);
+        const float e0 = __builtin_amdgcn_exp2f(
+            comp_logterm(cpar + (size_t)b0 * kParStride, x.x, x.y, x.z));
+        s += e0;
+        if (sl < SCAP) E[sl * RS + tx] = e0;
+      }
+    }
+    reds[rr * T + t] = s;
+    __syncthreads();
+
+    // ---- normaliser (waves of the first replica: one thread per point)
+    if (rr == 0) {
+      float st = reds[t];
+#pragma unroll
+      for (int j = 1; j < R; ++j) st += reds[j * T + t];
+      const bool fb = valid && !(st >= 0x1p-100f);
+      float mref = 0.0f;
+      if (fb) {
+        // far from every component: own maximum over all K (as the dense
+        // kernel's fallback); the point joins the statistics afterwards
+        float mx = -INFINITY;
+        for (int bb = 0; bb < K; ++bb)
+          mx = fmaxf(mx, comp_logterm(cpar + (size_t)bb * kParStride, x.x, x.y, x.z));
+        st = 0.0f;
+        for (int bb = 0; bb < K; ++bb)
+          st += __builtin_amdgcn_exp2f(
+              comp_logterm(cpar + (size_t)bb * kParStride, x.x, x.y, x.z) - mx);
+        mref = mx;
+        fbv[t] = make_float2(mx, st);
+      }
+      Xs[tx] = make_float4(x.x, x.y, x.z,
+                           (valid && !fb) ? __builtin_amdgcn_rcpf(st) : 0.0f);
+      const uint64_t fm = __ballot(fb);
+      if (lane == 0) fbmask[pg] = fm;
+      if (valid) {
+        const double lse = (Cb + (double)mref + (double)__builtin_amdgcn_logf(st)) * kLn2;
+        Lacc += lse;
+        if (lse_out) lse_out[(size_t)tile * T + t] = (float)lse;
+      }
+    }
+    __syncthreads();
+
+    // ---- M-phase over the active list, SCAP slots at a time
+    if (tid == 0) npairs += (unsigned)nact;
+    if (mode != kSoftLogLik) {
+      const int q = tid % P;
+      for (int c0 = 0; c0 < nact; c0 += SCAP) {
+        const int nloc = min(SCAP, nact - c0);
+        if (c0 > 0) {
+          // rows of the slots [c0, c0 + nloc): recomputed, the normaliser is known
+          __syncthreads();
+          for (int u = w; u < nloc * W; u += NW) {
+            const int sl = u / W, g2 = u % W;
+            const int b = __builtin_amdgcn_readfirstlane(list[c0 + sl]);
+            const int t2 = g2 * 64 + lane, c2 = t2 + t2 / TRIP;
+            const float4 xp = Xs[c2];
+            E[sl * RS + c2] = __builtin_amdgcn_exp2f(
+                comp_logterm(cpar + (size_t)b * kParStride, xp.x, xp.y, xp.z));
+          }
+          __syncthreads();
+        }
+        for (int s0 = 0; s0 < nloc; s0 += SLOTS) {
+          const int sl = s0 + tid / P;
+          if (sl < nloc) {
+            const int b = list[c0 + sl];
+            const float4 sh = ShL[b];
+            const float *Eb = E + sl * RS + q * (TRIP + 1);
+            const float4 *Xb = Xs + q * (TRIP + 1);
+            float av[kNStat];
+#pragma unroll
+            for (int j = 0; j < kNStat; ++j) av[j] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < TRIP; ++j) {
+              const float4 xr = Xb[j];
+              const float gm = Eb[j] * xr.w;
+              const float d0 = xr.x - sh.x, d1 = xr.y - sh.y, d2 = xr.z - sh.z;
+              const float w0 = gm * d0, w1 = gm * d1, w2 = gm * d2;
+              av[0] += gm;
+              av[1] += w0; av[2] += w1; av[3] += w2;
+              av[4] = fmaf(w0, d0, av[4]);
+              av[5] = fmaf(w1, d0, av[5]);
+              av[6] = fmaf(w1, d1, av[6]);
+              av[7] = fmaf(w2, d0, av[7]);
+              av[8] = fmaf(w2, d1, av[8]);
+              av[9] = fmaf(w2, d2, av[9]);
+            }
+            subset_sum<P>(av);
+            // lane q adds statistic q (and q + 8 when P = 8)
+            float u0 = av[0];
+#pragma unroll
+            for (int j = 1; j < kNStat; ++j) u0 = (q == j) ? av[j] : u0;
+            double *ab = acc + (size_t)b * kNStat;
+            if (q < kNStat) ab[q] += (double)u0;
+            if (P == 8 && q < 2) ab[q + 8] += (double)(q == 0 ? av[8] : av[9]);
+          }
+        }
+      }
+    }
+    // ---- cull of the next tile
+    const bool more = tile + grid < ntiles;
+    if (more && w < nchk) {
+      const uint64_t m = cull_ballot(CP + 3 * ((w << 6) + lane), spn);
+      if (lane == 0) masks[w] = m;
+    }
+    if (tile + 2 * grid < ntiles) spn = sph[tile + 2 * grid];
+    __syncthreads();
+
+    // ---- far points of this tile (rare): wave 0, one lane per component
+    if (mode != kSoftLogLik && w == 0) {
+      for (int g2 = 0; g2 < W; ++g2) {
+        uint64_t fm = fbmask[g2];
+        while (fm) {
+          const int i = __builtin_ctzll(fm);
+          fm &= fm - 1;
+          const int t2 = g2 * 64 + i;
+          const float4 xp = Xs[t2 + t2 / TRIP];
+          const float2 v = fbv[t2];
+          const float inv = __builtin_amdgcn_rcpf(v.y);
+          for (int b = lane; b < K; b += 64) {
+            const float gm = __builtin_amdgcn_exp2f(
+                comp_logterm(cpar + (size_t)b * kParStride, xp.x, xp.y, xp.z) - v.x) * inv;
+            const float4 sh = ShL[b];
+            const float d0 = xp.x - sh.x, d1 = xp.y - sh.y, d2 = xp.z - sh.z;
+            double *ab = acc + (size_t)b * kNStat;
+            ab[0] += (double)gm;
+            ab[1] += (double)(gm * d0); ab[2] += (double)(gm * d1); ab[3] += (double)(gm * d2);
+            ab[4] += (double)(gm * d0 * d0); ab[5] += (double)(gm * d1 * d0);
+            ab[6] += (double)(gm * d1 * d1); ab[7] += (double)(gm * d2 * d0);
+            ab[8] += (double)(gm * d2 * d1); ab[9] += (double)(gm * d2 * d2);
+          }
+        }
+      }
+    }
+    // ---- active list of the next tile
+    if (more) build_list();
+    __syncthreads();
+  }
+
+  // ---- this block's partial row
+  double *row = part + (size_t)blockIdx.x * a.ncols;
+  if (mode != kSoftLogLik) {
+    for (int i = tid; i < K * kNStat; i += BLOCK) {
+      const int j = i / K, b = i - j * K;
+      row[i] = acc[(size_t)b * kNStat + j];
+    }
+  }
+  double v = Lacc;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) wL[w] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int j = 0; j < NW; ++j) sum += wL[j];
+    row[kNStat * K] = sum;
+    if (a.pairs) atomicAdd(a.pairs, npairs);
+  }
 }
 
 // ------------------------------------------------------ reduction kernels

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "em_device.hpp"
+#include "order_device.hpp"
 #include "gmm.h"
 
 namespace {
@@ -76,6 +77,11 @@ struct Profiler {
   double ms_total = 0.0;
   int64_t launches = 0;
   std::vector<EventPair> pending;
+  // (tile, component) pairs of the timed launches: all, and those the dense
+  // kernel evaluated; the culled kernel adds its own to a device counter
+  int64_t pairs_all = 0, pairs_dense = 0;
+  unsigned long long *dpairs = nullptr;
+  int dpairs_dev = -1;
 };
 thread_local Profiler g_prof;
 
@@ -395,12 +401,95 @@ bool pick_cfg(int K, int64_t n, TileCfg *out) {
   return d >= 0 && kCand[d](K, n, out);
 }
 
+// Launch configuration of the culled tile kernel (soft E+M passes).
+struct CullCfg {
+  int block = 0, tile = 0, trip = 0, grid = 0;
+  size_t lds = 0;
+  const char *name = "";
+  void (*launch)(const CullCfg &, hipStream_t, const float4 *, const float4 *,
+                 const float *, const float4 *, double *, float *,
+                 const TileArgs &) = nullptr;
+};
+
+template <int BLOCK, int T, int TRIP, int SCAP>
+void launch_cull(const CullCfg &c, hipStream_t s, const float4 *pts,
+                 const float4 *sph, const float *cpar, const float4 *shift,
+                 double *part, float *lse, const TileArgs &a) {
+  hipLaunchKernelGGL((em_cull_kernel<BLOCK, T, TRIP, SCAP>), dim3(c.grid),
+                     dim3(BLOCK), c.lds, s, pts, sph, cpar, shift, part, lse, a);
+}
+
+template <int BLOCK, int T, int TRIP, int SCAP>
+bool make_cull_cfg(int K, int64_t n, CullCfg *out) {
+  DevInfo di = dev_info();
+  if (di.cus <= 0 || K > BLOCK) return false;  // one 64-component chunk per wave
+  const size_t lds = cull_lds_bytes<BLOCK, T, TRIP, SCAP>(K);
+  if (lds > (di.lds_max ? di.lds_max : 65536)) return false;
+  const void *fn = reinterpret_cast<const void *>(&em_cull_kernel<BLOCK, T, TRIP, SCAP>);
+  if (lds > 65536 &&
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds) != hipSuccess)
+    return false;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BLOCK, lds) !=
+          hipSuccess || per_cu <= 0)
+    return false;
+  const int64_t ntiles = (n + T - 1) / T;
+  out->block = BLOCK;
+  out->tile = T;
+  out->trip = TRIP;
+  out->grid = (int)std::min<int64_t>(ntiles, (int64_t)di.cus * per_cu);
+  out->lds = lds;
+  out->launch = &launch_cull<BLOCK, T, TRIP, SCAP>;
+  return true;
+}
+
+using MakeCull = bool (*)(int, int64_t, CullCfg *);
+constexpr int kNumCull = 8;
+const MakeCull kCull[kNumCull] = {
+    &make_cull_cfg<512, 128, 16, 64>, &make_cull_cfg<512, 256, 16, 32>,
+    &make_cull_cfg<512, 128, 16, 32>, &make_cull_cfg<1024, 128, 16, 64>,
+    &make_cull_cfg<512, 128, 8, 32>,  &make_cull_cfg<256, 128, 16, 32>,
+    &make_cull_cfg<256, 128, 8, 32>,  &make_cull_cfg<256, 64, 8, 32>};
+const char *const kCullName[kNumCull] = {"c512t128",    "c512t256",    "c512t128s32",
+                                         "c1024t128",   "c512t128p16", "c256t128",
+                                         "c256t128p16", "c256t64"};
+
+// Culling is on unless GMM_CULL=0 or GMM_TILE_SHAPE names a dense shape.
+bool pick_cull_cfg(int K, int64_t n, CullCfg *out) {
+  const char *off = getenv("GMM_CULL");
+  if (off && off[0] == '0') return false;
+  const char *e = getenv("GMM_TILE_SHAPE");
+  if (e && *e) {
+    for (int i = 0; i < kNumCull; ++i)
+      if (strcmp(e, kCullName[i]) == 0) {
+        if (!kCull[i](K, n, out)) return false;
+        out->name = kCullName[i];
+        return true;
+      }
+    return false;
+  }
+  // measured on the depth frame: subsets of 8 points up to K = 128, of 16
+  // above; 1024-thread blocks beyond K = 512
+  const int order[2] = {K <= 128 ? 4 : K <= 512 ? 0 : 3, 3};
+  for (int i : order)
+    if (kCull[i](K, n, out)) {
+      out->name = kCullName[i];
+      return true;
+    }
+  return false;
+}
+
 // Largest grid over every runnable candidate: the workspace fits any of them.
 int max_grid(int K, int64_t n) {
   int g = 0;
   for (int i = 0; i < kNumCand; ++i) {
     TileCfg c;
     if (kCand[i](K, n, &c)) g = std::max(g, c.grid);
+  }
+  for (int i = 0; i < kNumCull; ++i) {
+    CullCfg c;
+    if (kCull[i](K, n, &c)) g = std::max(g, c.grid);
   }
   return g;
 }
@@ -409,18 +498,24 @@ int max_grid(int K, int64_t n) {
 // writes the other), the FP64 state, the partial rows and the staged points.
 struct WsLayout {
   size_t status, counter, pose64, rt32, cpar[2], shift[2], th64, red, part,
-      pts4, total;
+      pts4, tsph, total;
+  // spatial ordering (fits): unsorted staging, keys/indices, digit counts
+  size_t raw4 = 0, keys[2] = {0, 0}, vals[2] = {0, 0}, hist = 0, box6 = 0;
+  int sort_blocks = 0;
   int64_t npad;
   int ncols, nslots;
 };
 
+// Largest point count the fit orders spatially (single-block digit scan).
+constexpr int64_t kSortMaxN = (int64_t)1 << 26;
+
 WsLayout ws_layout(int64_t n, int K, const TileCfg &c, int extra_cols = 0,
-                   int grid_override = 0) {
+                   int grid_override = 0, bool with_sort = false) {
   WsLayout L{};
   size_t o = 0;
   L.ncols = kNStat * K + 1 + extra_cols;
   L.nslots = std::max(std::max(c.grid, grid_override), max_grid(K, n));
-  L.npad = ((n + 127) / 128) * 128;   // a multiple of every tile size
+  L.npad = ((n + 255) / 256) * 256;   // a multiple of every tile size
   L.status = o; o = align256(o + 256);
   L.counter = o; o = align256(o + sizeof(unsigned));
   L.pose64 = o; o = align256(o + 32 * sizeof(double));
@@ -433,6 +528,17 @@ WsLayout ws_layout(int64_t n, int K, const TileCfg &c, int extra_cols = 0,
   L.red = o; o = align256(o + (size_t)kRedChunks * L.ncols * sizeof(double));
   L.part = o; o = align256(o + (size_t)L.nslots * L.ncols * sizeof(double));
   L.pts4 = o; o = align256(o + (size_t)L.npad * sizeof(float4));
+  L.tsph = o; o = align256(o + (size_t)(L.npad / 64) * sizeof(float4));
+  if (with_sort && L.npad <= kSortMaxN) {
+    L.sort_blocks = (int)((L.npad + kSortChunk - 1) / kSortChunk);
+    L.raw4 = o; o = align256(o + (size_t)L.npad * sizeof(float4));
+    for (int i = 0; i < 2; ++i) {
+      L.keys[i] = o; o = align256(o + (size_t)L.npad * sizeof(unsigned));
+      L.vals[i] = o; o = align256(o + (size_t)L.npad * sizeof(unsigned));
+    }
+    L.hist = o; o = align256(o + (size_t)256 * L.sort_blocks * sizeof(unsigned));
+    L.box6 = o; o = align256(o + (size_t)kBoxBlocks * 6 * sizeof(float));
+  }
   L.total = o;
   return L;
 }
@@ -486,7 +592,9 @@ gmm_status check_sizes(int64_t n, int32_t k, bool fit) {
 
 // The state of one call: configuration, layout and the current parameter set.
 struct Run {
-  TileCfg c;
+  TileCfg c;      // dense tile kernel (label passes; all passes without culling)
+  CullCfg cc;     // culled tile kernel (soft passes), when `cull`
+  bool cull = false;
   WsLayout L;
   void *ws = nullptr;
   hipStream_t s = nullptr;
@@ -548,24 +656,37 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
                     float *lse, float *out_w = nullptr, float *out_mu = nullptr,
                     float *out_cov = nullptr) {
   const WsLayout &L = r.L;
+  const bool cull = r.cull && mode != kLabels;
   TileArgs a;
-  a.ntiles = (int)(L.npad / r.c.tile);
+  a.ntiles = (int)(L.npad / (cull ? r.cc.tile : r.c.tile));
   a.K = r.K;
   a.KC = r.c.KC;
   a.P = r.c.P;
   a.mode = mode;
   a.ncols = L.ncols;
+  const int rows = cull ? r.cc.grid : r.c.grid;  // partial rows written
   EventPair pp;
   const bool timed = r.sink && mode == kSoftStats;
   if (timed) {
     if (!make_pair(&pp)) return fail(GMM_ERR_DEVICE, "profiling event allocation failed");
     pp.reps = g_prof.reps;
     r.sink->push_back(pp);
+    const int64_t all = (int64_t)g_prof.reps * a.ntiles * r.K;
+    g_prof.pairs_all += all;
+    if (cull)
+      a.pairs = g_prof.dpairs;
+    else
+      g_prof.pairs_dense += all;
     HIP_TRY(hipEventRecord(pp.a, r.s));
   }
   for (int rep = 0; rep < (timed ? g_prof.reps : 1); ++rep) {
-    r.c.launch(r.c, r.s, at<float4>(r.ws, L.pts4), at<float>(r.ws, L.cpar[r.cur]),
-               at<float4>(r.ws, L.shift[r.cur]), at<double>(r.ws, L.part), lse, a);
+    if (cull)
+      r.cc.launch(r.cc, r.s, at<float4>(r.ws, L.pts4), at<float4>(r.ws, L.tsph),
+                  at<float>(r.ws, L.cpar[r.cur]), at<float4>(r.ws, L.shift[r.cur]),
+                  at<double>(r.ws, L.part), lse, a);
+    else
+      r.c.launch(r.c, r.s, at<float4>(r.ws, L.pts4), at<float>(r.ws, L.cpar[r.cur]),
+                 at<float4>(r.ws, L.shift[r.cur]), at<double>(r.ws, L.part), lse, a);
     HIP_TRY(hipGetLastError());
   }
   if (timed) HIP_TRY(hipEventRecord(pp.b, r.s));
@@ -573,7 +694,7 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   const int col0 = (mode == kSoftLogLik) ? kNStat * r.K : 0;
   const int ncx = (L.ncols - col0 + 63) / 64;
   hipLaunchKernelGGL(reduce_rows_kernel, dim3(ncx, kRedChunks), dim3(256), 0,
-                     r.s, at<double>(r.ws, L.part), r.c.grid, L.ncols, col0,
+                     r.s, at<double>(r.ws, L.part), rows, L.ncols, col0,
                      at<double>(r.ws, L.red));
   HIP_TRY(hipGetLastError());
   UpdPtrs q;
@@ -622,13 +743,69 @@ gmm_status run_precompute(Run &r, const float *w, const float *mu,
   return GMM_OK;
 }
 
+// Morton order of the staged points: raw4 -> pts4 (see order_device.hpp).
+gmm_status spatial_order(Run &r, int64_t n) {
+  const WsLayout &L = r.L;
+  const int64_t npad = L.npad;
+  const int nblk = L.sort_blocks;
+  hipLaunchKernelGGL(bbox_kernel, dim3(kBoxBlocks), dim3(kSortThreads), 0, r.s,
+                     at<float4>(r.ws, L.raw4), n, at<float>(r.ws, L.box6));
+  HIP_TRY(hipGetLastError());
+  const unsigned mb = (unsigned)std::min<int64_t>(256, (npad + kSortThreads - 1) / kSortThreads);
+  hipLaunchKernelGGL(morton_kernel, dim3(mb), dim3(kSortThreads), 0, r.s,
+                     at<float4>(r.ws, L.raw4), n, npad, at<float>(r.ws, L.box6),
+                     kBoxBlocks, at<unsigned>(r.ws, L.keys[0]),
+                     at<unsigned>(r.ws, L.vals[0]));
+  HIP_TRY(hipGetLastError());
+  int src = 0;
+  for (int shift = 0; shift < 24; shift += 8, src = 1 - src) {
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kSortThreads), 0, r.s,
+                       at<unsigned>(r.ws, L.keys[src]), npad, shift,
+                       at<unsigned>(r.ws, L.hist), nblk);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(radix_scan_kernel, dim3(1), dim3(kScanThreads), 0, r.s,
+                       at<unsigned>(r.ws, L.hist), 256 * nblk);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, r.s,
+                       at<unsigned>(r.ws, L.keys[src]), at<unsigned>(r.ws, L.vals[src]),
+                       npad, shift, at<unsigned>(r.ws, L.hist), nblk,
+                       at<unsigned>(r.ws, L.keys[1 - src]),
+                       at<unsigned>(r.ws, L.vals[1 - src]));
+    HIP_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((npad + kSortThreads - 1) / kSortThreads)),
+                     dim3(kSortThreads), 0, r.s, at<float4>(r.ws, L.raw4),
+                     at<unsigned>(r.ws, L.vals[src]), npad, at<float4>(r.ws, L.pts4));
+  HIP_TRY(hipGetLastError());
+  return GMM_OK;
+}
+
+// Spatial ordering is used by culled fits unless GMM_SORT=0.
+bool sort_enabled() {
+  const char *e = getenv("GMM_SORT");
+  return !(e && e[0] == '0');
+}
+
 gmm_status stage(Run &r, const float *pts, int64_t n, const int32_t *labels,
-                 const float *Rt) {
+                 const float *Rt, bool sort = false) {
   const int64_t nb = (r.L.npad + 255) / 256;
+  sort = sort && r.cull && r.L.sort_blocks > 0;
   hipLaunchKernelGGL(stage_kernel, dim3((unsigned)nb), dim3(256), 0, r.s, pts,
-                     n, r.L.npad, labels, r.K, Rt, at<float4>(r.ws, r.L.pts4),
+                     n, r.L.npad, labels, r.K, Rt,
+                     at<float4>(r.ws, sort ? r.L.raw4 : r.L.pts4),
                      at<uint32_t>(r.ws, r.L.status));
   HIP_TRY(hipGetLastError());
+  if (sort) {
+    gmm_status st = spatial_order(r, n);
+    if (st != GMM_OK) return st;
+  }
+  if (r.cull) {
+    const int64_t nt = r.L.npad / r.cc.tile;
+    hipLaunchKernelGGL(tile_sphere_kernel, dim3((unsigned)nt), dim3(256), 0, r.s,
+                       at<float4>(r.ws, r.L.pts4), r.cc.tile,
+                       at<float4>(r.ws, r.L.tsph));
+    HIP_TRY(hipGetLastError());
+  }
   return GMM_OK;
 }
 
@@ -648,7 +825,7 @@ gmm_status enqueue_fit(Run &r, const float *pts, int64_t n,
                        bool may_tune) {
   gmm_status st;
   if ((st = run_init(r, init_labels != nullptr)) != GMM_OK) return st;
-  if ((st = stage(r, pts, n, init_labels, nullptr)) != GMM_OK) return st;
+  if ((st = stage(r, pts, n, init_labels, nullptr, sort_enabled())) != GMM_OK) return st;
   const double reg = opts->reg_covar;
   if (init_labels) {
     // theta_0 = M-step of the one-hot responsibilities, two passes: the mean
@@ -658,7 +835,7 @@ gmm_status enqueue_fit(Run &r, const float *pts, int64_t n,
   } else {
     if ((st = run_precompute(r, w, mu, cov)) != GMM_OK) return st;
   }
-  if (may_tune && autotune_on() && forced_candidate() < 0 &&
+  if (may_tune && !r.cull && autotune_on() && forced_candidate() < 0 &&
       tuned_candidate(r.K, n) < 0 &&
       (st = autotune(r, n)) != GMM_OK)
     return st;
@@ -686,11 +863,14 @@ struct FitKey {
   size_t ws_bytes;
   double reg;
   int k, iters, mode, dev;
+  const void *dense, *culled;  // the kernels the fit launches
+  bool sorted;
   bool operator==(const FitKey &o) const {
     return pts == o.pts && labels == o.labels && w == o.w && mu == o.mu &&
            cov == o.cov && loglik == o.loglik && ws == o.ws && n == o.n &&
            ws_bytes == o.ws_bytes && reg == o.reg && k == o.k &&
-           iters == o.iters && mode == o.mode && dev == o.dev;
+           iters == o.iters && mode == o.mode && dev == o.dev &&
+           dense == o.dense && culled == o.culled && sorted == o.sorted;
   }
 };
 
@@ -1037,7 +1217,7 @@ size_t gmm_fit_workspace_size(int64_t n, int32_t k, const gmm_fit_opts *opts) {
   if (check_sizes(n, k, true) != GMM_OK) return 0;
   TileCfg c;
   if (!pick_cfg(k, n, &c)) return 0;
-  return ws_layout(n, k, c).total;
+  return ws_layout(n, k, c, 0, 0, true).total;
 }
 
 gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
@@ -1059,7 +1239,8 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
   Run r;
   r.K = k;
   if (!pick_cfg(k, n, &r.c)) return fail(GMM_ERR_UNSUPPORTED, "no launch configuration for k=%d", k);
-  r.L = ws_layout(n, k, r.c);
+  r.cull = pick_cull_cfg(k, n, &r.cc);
+  r.L = ws_layout(n, k, r.c, 0, 0, true);
   r.s = static_cast<hipStream_t>(stream);
   WsGuard guard;
   if ((st = get_ws(&ws, &ws_bytes, r.L.total, r.s, &guard)) != GMM_OK) return st;
@@ -1070,7 +1251,10 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
   // that a captured graph records.
   if (graphs_enabled() && !guard.ptr && g_prof.reps == 0) {
     FitKey key{pts, init_labels, w, mu, cov, loglik, ws, n, ws_bytes,
-               opts->reg_covar, k, opts->iters, opts->moment_mode, 0};
+               opts->reg_covar, k, opts->iters, opts->moment_mode, 0,
+               reinterpret_cast<const void *>(r.c.launch),
+               r.cull ? reinterpret_cast<const void *>(r.cc.launch) : nullptr,
+               sort_enabled()};
     (void)hipGetDevice(&key.dev);
     std::lock_guard<std::mutex> lk(g_graph_mu);
     bool found = false;
@@ -1121,6 +1305,7 @@ gmm_status gmm_loglik(const float *pts, int64_t n, const float *pose6,
   Run r;
   r.K = k;
   if (!pick_cfg(k, n, &r.c)) return fail(GMM_ERR_UNSUPPORTED, "no launch configuration for k=%d", k);
+  r.cull = pick_cull_cfg(k, n, &r.cc);
   r.L = ws_layout(n, k, r.c);
   r.s = static_cast<hipStream_t>(stream);
   WsGuard guard;
@@ -1249,6 +1434,8 @@ const char *gmm_tile_config(int64_t n, int32_t k) {
   g_err[0] = 0;
   if (check_sizes(n, k, false) != GMM_OK) return "";
   TileCfg c;
+  CullCfg cc;
+  if (pick_cull_cfg(k, n, &cc)) return cc.name;
   const int f = forced_candidate();
   if (f >= 0 && kCand[f](k, n, &c)) return kCandName[f];
   const int t = tuned_candidate(k, n);
@@ -1261,7 +1448,32 @@ gmm_status gmm_profile_enable(int reps) {
   g_err[0] = 0;
   if (reps < 0 || reps > 64)
     return fail(GMM_ERR_INVALID_ARG, "profile repeats must be in [0, 64] (got %d)", reps);
+  if (reps > 0) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (!g_prof.dpairs || g_prof.dpairs_dev != dev) {
+      unsigned long long *p = nullptr;
+      HIP_TRY(hipMalloc(&p, sizeof(unsigned long long)));
+      HIP_TRY(hipMemset(p, 0, sizeof(unsigned long long)));
+      g_prof.dpairs = p;  // one counter per thread and device, kept
+      g_prof.dpairs_dev = dev;
+    }
+  }
   g_prof.reps = reps;
+  return GMM_OK;
+}
+
+gmm_status gmm_profile_pairs(int64_t *evaluated, int64_t *all) {
+  g_err[0] = 0;
+  unsigned long long dev_pairs = 0;
+  if (g_prof.dpairs) {
+    HIP_TRY(hipMemcpy(&dev_pairs, g_prof.dpairs, sizeof dev_pairs, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(g_prof.dpairs, 0, sizeof(unsigned long long)));
+  }
+  if (evaluated) *evaluated = g_prof.pairs_dense + (int64_t)dev_pairs;
+  if (all) *all = g_prof.pairs_all;
+  g_prof.pairs_dense = 0;
+  g_prof.pairs_all = 0;
   return GMM_OK;
 }
 

@@ -1,0 +1,221 @@
+// Spatial ordering of the staged points (device code, included by gmm.hip).
+//
+// Tile culling skips (tile, component) pairs by a bound on the tile's
+// bounding sphere, so it pays only when consecutive points are close in
+// space.  Before a culled fit, the staged points are put in Morton
+// (Z-order) order of a 256^3 grid over their bounding box:
+//   bbox_kernel      per-block partial boxes (no atomics);
+//   morton_kernel    every block reduces the partial boxes, then the 24-bit
+//                    key of each point (padding gets the largest key);
+//   radix passes     a stable LSD radix sort of (key, index), three 8-bit
+//                    digits: per-block digit counts, one exclusive scan in
+//                    (digit, block) order, a stable scatter (ranks from wave
+//                    ballots, waves and rounds in item order);
+//   gather_kernel    the points in sorted order.
+// Every step is deterministic, so a fit is still bitwise reproducible, and
+// no step clears memory with a memset (the fit may be captured in a graph).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gmm_dev {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;                          // per thread and pass
+constexpr int kSortChunk = kSortThreads * kSortItems;   // items per block
+constexpr int kBoxBlocks = 256;
+constexpr int kScanThreads = 1024;
+
+__device__ inline void box_update(float4 x, float *lo, float *hi) {
+  lo[0] = fminf(lo[0], x.x); lo[1] = fminf(lo[1], x.y); lo[2] = fminf(lo[2], x.z);
+  hi[0] = fmaxf(hi[0], x.x); hi[1] = fmaxf(hi[1], x.y); hi[2] = fmaxf(hi[2], x.z);
+}
+
+// Min / max over a 256-thread block; thread 0 gets the result.
+__device__ inline void box_block_reduce(float *lo, float *hi, float *sh /*4 x 6*/) {
+  for (int off = 32; off > 0; off >>= 1)
+    for (int j = 0; j < 3; ++j) {
+      lo[j] = fminf(lo[j], __shfl_xor(lo[j], off, 64));
+      hi[j] = fmaxf(hi[j], __shfl_xor(hi[j], off, 64));
+    }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int j = 0; j < 3; ++j) {
+      sh[w * 6 + j] = lo[j];
+      sh[w * 6 + 3 + j] = hi[j];
+    }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int v = 1; v < kSortThreads / 64; ++v)
+      for (int j = 0; j < 3; ++j) {
+        lo[j] = fminf(lo[j], sh[v * 6 + j]);
+        hi[j] = fmaxf(hi[j], sh[v * 6 + 3 + j]);
+      }
+}
+
+// Partial bounding boxes of the n real points: part6[block] = (lo, hi).
+__global__ __launch_bounds__(kSortThreads) void bbox_kernel(
+    const float4 *__restrict__ pts, int64_t n, float *__restrict__ part6) {
+  __shared__ float sh[kSortThreads / 64 * 6];
+  float lo[3] = {INFINITY, INFINITY, INFINITY};
+  float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kSortThreads)
+    box_update(pts[i], lo, hi);
+  box_block_reduce(lo, hi, sh);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 3; ++j) {
+      part6[blockIdx.x * 6 + j] = lo[j];
+      part6[blockIdx.x * 6 + 3 + j] = hi[j];
+    }
+}
+
+// 8 bits of v spread to every third bit.
+__device__ inline unsigned spread3(unsigned v) {
+  v &= 0xFFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// keys[i] = Morton code of point i in a cubic 256^3 grid over the box of
+// the real points, 0xFFFFFF for padding; vals[i] = i.
+__global__ __launch_bounds__(kSortThreads) void morton_kernel(
+    const float4 *__restrict__ pts, int64_t n, int64_t npad,
+    const float *__restrict__ part6, int nbox, unsigned *__restrict__ keys,
+    unsigned *__restrict__ vals) {
+  __shared__ float sh[kSortThreads / 64 * 6];
+  __shared__ float box[4];
+  float lo[3] = {INFINITY, INFINITY, INFINITY};
+  float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = threadIdx.x; b < nbox; b += kSortThreads) {
+    for (int j = 0; j < 3; ++j) {
+      lo[j] = fminf(lo[j], part6[b * 6 + j]);
+      hi[j] = fmaxf(hi[j], part6[b * 6 + 3 + j]);
+    }
+  }
+  box_block_reduce(lo, hi, sh);
+  if (threadIdx.x == 0) {
+    const float ext = fmaxf(fmaxf(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
+    box[0] = lo[0];
+    box[1] = lo[1];
+    box[2] = lo[2];
+    box[3] = (ext > 0.0f && ext < INFINITY) ? 255.99f / ext : 0.0f;
+  }
+  __syncthreads();
+  const float l0 = box[0], l1 = box[1], l2 = box[2], sc = box[3];
+  for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < npad;
+       i += (int64_t)gridDim.x * kSortThreads) {
+    unsigned key = 0xFFFFFFu;
+    if (i < n) {
+      const float4 x = pts[i];
+      const unsigned q0 = (unsigned)fminf(fmaxf((x.x - l0) * sc, 0.0f), 255.0f);
+      const unsigned q1 = (unsigned)fminf(fmaxf((x.y - l1) * sc, 0.0f), 255.0f);
+      const unsigned q2 = (unsigned)fminf(fmaxf((x.z - l2) * sc, 0.0f), 255.0f);
+      key = spread3(q0) | (spread3(q1) << 1) | (spread3(q2) << 2);
+    }
+    keys[i] = key;
+    vals[i] = (unsigned)i;
+  }
+}
+
+// Digit counts of one block's chunk: hist[digit * nblk + block].
+__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
+    const unsigned *__restrict__ keys, int64_t npad, int shift,
+    unsigned *__restrict__ hist, int nblk) {
+  __shared__ unsigned h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t i = base + it * kSortThreads + threadIdx.x;
+    if (i < npad) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// In-place exclusive scan of hist[0 .. total) (one block).
+__global__ __launch_bounds__(kScanThreads) void radix_scan_kernel(unsigned *hist,
+                                                                  int total) {
+  __shared__ unsigned sums[kScanThreads];
+  const int seg = (total + kScanThreads - 1) / kScanThreads;
+  const int a = threadIdx.x * seg, b = min(total, a + seg);
+  unsigned s = 0;
+  for (int i = a; i < b; ++i) s += hist[i];
+  sums[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {  // inclusive, Hillis-Steele
+    const unsigned v = threadIdx.x >= off ? sums[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sums[threadIdx.x] += v;
+    __syncthreads();
+  }
+  unsigned run = threadIdx.x ? sums[threadIdx.x - 1] : 0u;
+  for (int i = a; i < b; ++i) {
+    const unsigned v = hist[i];
+    hist[i] = run;
+    run += v;
+  }
+}
+
+// Stable scatter of one block's chunk by the digit at `shift`.  Items are
+// taken in rounds of one per thread; within a round an item's rank among
+// equal digits comes from wave ballots (lower lanes first) and the counts
+// of the lower waves, after every item of the earlier rounds.
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
+    const unsigned *__restrict__ kin, const unsigned *__restrict__ vin,
+    int64_t npad, int shift, const unsigned *__restrict__ off, int nblk,
+    unsigned *__restrict__ kout, unsigned *__restrict__ vout) {
+  constexpr int W = kSortThreads / 64;
+  __shared__ unsigned run[256];
+  __shared__ unsigned wc[W][256];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  run[tid] = off[(size_t)tid * nblk + blockIdx.x];
+  for (int v = 0; v < W; ++v) wc[v][tid] = 0u;
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t i = base + it * kSortThreads + tid;
+    const bool ok = i < npad;
+    const unsigned k = ok ? kin[i] : 0u;
+    const unsigned d = (k >> shift) & 255u;
+    uint64_t pm = __ballot(ok);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const uint64_t bm = __ballot((d >> bit) & 1u);
+      pm &= ((d >> bit) & 1u) ? bm : ~bm;
+    }
+    const unsigned rank = (unsigned)__popcll(pm & lt);
+    const bool last = ((pm >> lane) >> 1) == 0ull;
+    if (ok && last) wc[w][d] = rank + 1u;
+    __syncthreads();
+    if (ok) {
+      unsigned pos = run[d] + rank;
+      for (int v = 0; v < w; ++v) pos += wc[v][d];
+      kout[pos] = k;
+      vout[pos] = vin[i];
+    }
+    __syncthreads();
+    unsigned add = 0u;
+    for (int v = 0; v < W; ++v) {
+      add += wc[v][tid];
+      wc[v][tid] = 0u;
+    }
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+// out[i] = in[perm[i]]
+__global__ __launch_bounds__(kSortThreads) void gather_kernel(
+    const float4 *__restrict__ in, const unsigned *__restrict__ perm,
+    int64_t npad, float4 *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+  if (i < npad) out[i] = in[perm[i]];
+}
+
+}  // namespace gmm_dev

@@ -309,9 +309,10 @@ def test_graph_replay_matches_direct_launches():
 
 
 SHAPES = ["b512t64", "b1024t128", "b512t128", "b256t64", "b1024t64", "b1024t64c2"]
+CULL_SHAPES = ["c512t128", "c512t256", "c512t128s32", "c1024t128", "c512t128p16", "c256t128", "c256t128p16", "c256t64"]
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + CULL_SHAPES)
 @pytest.mark.parametrize("K,n", [(100, 20011), (16, 5003), (200, 12000), (700, 9000)])
 def test_every_tile_shape_one_step_parity(shape, K, n, monkeypatch):
     """Each tile shape the autotuner may pick meets the one-step bar."""
@@ -330,6 +331,7 @@ def test_autotune_picks_a_shape_and_keeps_parity(monkeypatch, tmp_path):
     _case("autotune")
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("GMM_AUTOTUNE_CACHE", str(cache))
+    monkeypatch.setenv("GMM_CULL", "0")     # the tuner picks among dense shapes
     _lib.set_autotune(True)
     try:
         X = _depth_subset(30011, seed=21)
@@ -360,3 +362,43 @@ def test_poisoned_workspace_does_not_leak(K, n):
     L = r.loglik.cpu().numpy()
     assert np.abs(L - Lr).max() / max(np.abs(Lr).max(), n) <= 1e-5
     assert _rel(r.means.cpu().numpy(), mur) <= 1e-5
+
+
+# ------------------------------------------------------------ tile culling
+
+@pytest.mark.parametrize("K,n,order", [(100, 60013, "pixel"), (100, 60013, "shuffled"),
+                                       (37, 9001, "pixel"), (256, 30000, "pixel")])
+def test_culled_matches_dense_and_oracle(K, n, order, monkeypatch):
+    """The culled kernel skips only pairs whose FP32 weight is exactly zero:
+    one step agrees with the oracle to the one-step bar and with the dense
+    kernel to FP32 summation-order level."""
+    _case("cull vs dense K=%d n=%d %s" % (K, n, order))
+    X = _depth_subset(n, seed=K + 31)
+    if order == "shuffled":
+        X = np.ascontiguousarray(X[np.random.default_rng(3).permutation(n)])
+    lab = synth.kmeanspp_labels(X, K, 2)
+    theta = oracle.fit(X, K, 1e-3, 2, labels=lab)[:3]
+    assert _lib.tile_config(n, K).startswith("c")
+    e_cull = _one_step(X, K, theta)
+    monkeypatch.setenv("GMM_CULL", "0")
+    assert _lib.tile_config(n, K).startswith("b")
+    e_dense = _one_step(X, K, theta)
+    print(e_cull, e_dense)
+    assert max(e_cull.values()) <= 1e-5, e_cull
+    assert max(e_dense.values()) <= 1e-5, e_dense
+
+
+def test_culled_far_points_take_the_dense_fallback():
+    """Points far from every component (normaliser below 2^-100) make their
+    tile dense; the result still meets the one-step bar."""
+    _case("cull fallback")
+    X = _depth_subset(20000, seed=5)
+    K = 40
+    lab = synth.kmeanspp_labels(X, K, 2)
+    theta = oracle.fit(X, K, 1e-3, 2, labels=lab)[:3]
+    Xf = X.copy()
+    Xf[1000:1010] += np.float32(30.0)      # ten points 30 m away: one tile
+    Xf[7777] -= np.float32(25.0)
+    errs = _one_step(Xf, K, theta)
+    print(errs)
+    assert max(errs.values()) <= 1e-5, errs
