@@ -49,10 +49,10 @@ PROFILE_REPS = 16           # tile launches per timed event pair
 # 256 MiB device copy (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all
 # of them).  Valid only for the kernel source and tile shape it was taken
 # on: any other reports null.
-TRAFFIC = {"kernel_src_sha256": "d0701912365db466163a010b26c602ecb77dd063af69ec3bcca94f61635aee99",
-           "tile_shape": "b512t64", "N": 307200, "K": 100,
-           "fetch_kib": 2545.00, "fetch_factor": 2.0,
-           "write_kib": 6024.00, "write_factor": 1.0}
+TRAFFIC = {"kernel_src_sha256": "999b6dba2ca18654d84316b5ab5d2e89fe8557473bd4447adb383c81dc640fdb",
+           "tile_shape": "c512t128p16", "N": 307200, "K": 100,
+           "fetch_kib": 2655.08, "fetch_factor": 2.0,
+           "write_kib": 6044.21, "write_factor": 1.0}
 
 
 def parse():

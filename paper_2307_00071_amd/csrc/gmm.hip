@@ -480,6 +480,15 @@ bool pick_cull_cfg(int K, int64_t n, CullCfg *out) {
   return false;
 }
 
+// GMM_DEBUG=1: the launch configuration of each fit on stderr.
+void debug_cfg(const char *what, int K, int64_t n, const char *name, int grid,
+               int block, size_t lds) {
+  const char *e = getenv("GMM_DEBUG");
+  if (!e || e[0] != '1') return;
+  fprintf(stderr, "gmm: %s K=%d n=%lld kernel %s grid %d block %d lds %zu\n", what, K,
+          (long long)n, name, grid, block, lds);
+}
+
 // Largest grid over every runnable candidate: the workspace fits any of them.
 int max_grid(int K, int64_t n) {
   int g = 0;
@@ -500,14 +509,14 @@ struct WsLayout {
   size_t status, counter, pose64, rt32, cpar[2], shift[2], th64, red, part,
       pts4, tsph, total;
   // spatial ordering (fits): unsorted staging, keys/indices, digit counts
-  size_t raw4 = 0, keys[2] = {0, 0}, vals[2] = {0, 0}, hist = 0, box6 = 0;
+  size_t raw4 = 0, keys[2] = {0, 0}, vals[2] = {0, 0}, hist = 0, dtot = 0, box6 = 0;
   int sort_blocks = 0;
   int64_t npad;
   int ncols, nslots;
 };
 
 // Largest point count the fit orders spatially (single-block digit scan).
-constexpr int64_t kSortMaxN = (int64_t)1 << 26;
+constexpr int64_t kSortMaxN = (int64_t)1 << 30;
 
 WsLayout ws_layout(int64_t n, int K, const TileCfg &c, int extra_cols = 0,
                    int grid_override = 0, bool with_sort = false) {
@@ -537,6 +546,7 @@ WsLayout ws_layout(int64_t n, int K, const TileCfg &c, int extra_cols = 0,
       L.vals[i] = o; o = align256(o + (size_t)L.npad * sizeof(unsigned));
     }
     L.hist = o; o = align256(o + (size_t)256 * L.sort_blocks * sizeof(unsigned));
+    L.dtot = o; o = align256(o + 256 * sizeof(unsigned));
     L.box6 = o; o = align256(o + (size_t)kBoxBlocks * 6 * sizeof(float));
   }
   L.total = o;
@@ -763,13 +773,13 @@ gmm_status spatial_order(Run &r, int64_t n) {
                        at<unsigned>(r.ws, L.keys[src]), npad, shift,
                        at<unsigned>(r.ws, L.hist), nblk);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(radix_scan_kernel, dim3(1), dim3(kScanThreads), 0, r.s,
-                       at<unsigned>(r.ws, L.hist), 256 * nblk);
+    hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(kSortThreads), 0, r.s,
+                       at<unsigned>(r.ws, L.hist), nblk, at<unsigned>(r.ws, L.dtot));
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, r.s,
                        at<unsigned>(r.ws, L.keys[src]), at<unsigned>(r.ws, L.vals[src]),
                        npad, shift, at<unsigned>(r.ws, L.hist), nblk,
-                       at<unsigned>(r.ws, L.keys[1 - src]),
+                       at<unsigned>(r.ws, L.dtot), at<unsigned>(r.ws, L.keys[1 - src]),
                        at<unsigned>(r.ws, L.vals[1 - src]));
     HIP_TRY(hipGetLastError());
   }
@@ -1240,6 +1250,7 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
   r.K = k;
   if (!pick_cfg(k, n, &r.c)) return fail(GMM_ERR_UNSUPPORTED, "no launch configuration for k=%d", k);
   r.cull = pick_cull_cfg(k, n, &r.cc);
+  if (r.cull) debug_cfg("fit", k, n, r.cc.name, r.cc.grid, r.cc.block, r.cc.lds);
   r.L = ws_layout(n, k, r.c, 0, 0, true);
   r.s = static_cast<hipStream_t>(stream);
   WsGuard guard;

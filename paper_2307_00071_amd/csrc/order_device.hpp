@@ -8,8 +8,9 @@
 //   morton_kernel    every block reduces the partial boxes, then the 24-bit
 //                    key of each point (padding gets the largest key);
 //   radix passes     a stable LSD radix sort of (key, index), three 8-bit
-//                    digits: per-block digit counts, one exclusive scan in
-//                    (digit, block) order, a stable scatter (ranks from wave
+//                    digits: per-block digit counts, a scan over the blocks
+//                    of each digit (one block per digit), a stable scatter
+//                    (digit starts from the digit totals; ranks from wave
 //                    ballots, waves and rounds in item order);
 //   gather_kernel    the points in sorted order.
 // Every step is deterministic, so a fit is still bitwise reproducible, and
@@ -22,10 +23,9 @@
 namespace gmm_dev {
 
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;                          // per thread and pass
+constexpr int kSortItems = 8;                           // per thread and pass
 constexpr int kSortChunk = kSortThreads * kSortItems;   // items per block
 constexpr int kBoxBlocks = 256;
-constexpr int kScanThreads = 1024;
 
 __device__ inline void box_update(float4 x, float *lo, float *hi) {
   lo[0] = fminf(lo[0], x.x); lo[1] = fminf(lo[1], x.y); lo[2] = fminf(lo[2], x.z);
@@ -137,28 +137,64 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
   hist[(size_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// In-place exclusive scan of hist[0 .. total) (one block).
-__global__ __launch_bounds__(kScanThreads) void radix_scan_kernel(unsigned *hist,
-                                                                  int total) {
-  __shared__ unsigned sums[kScanThreads];
-  const int seg = (total + kScanThreads - 1) / kScanThreads;
-  const int a = threadIdx.x * seg, b = min(total, a + seg);
-  unsigned s = 0;
-  for (int i = a; i < b; ++i) s += hist[i];
-  sums[threadIdx.x] = s;
+// Per-digit scan: block d turns hist[d * nblk .. (d + 1) * nblk) into its
+// exclusive prefix (in place) and writes the digit total dtot[d].  Each
+// thread takes a contiguous run of kScanPer counts; runs are scanned within
+// a wave by shuffles and across the block's waves by wave 0.
+constexpr int kScanPer = 8;
+
+__device__ inline unsigned wave_inclusive_scan(unsigned v, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block (four
+// waves); *total gets the block sum.  Two barriers.
+__device__ inline unsigned block_exclusive_scan256(unsigned v, unsigned *wsum,
+                                                   unsigned *total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned inc = wave_inclusive_scan(v, lane);
+  if (lane == 63) wsum[wv] = inc;
   __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {  // inclusive, Hillis-Steele
-    const unsigned v = threadIdx.x >= off ? sums[threadIdx.x - off] : 0u;
-    __syncthreads();
-    sums[threadIdx.x] += v;
-    __syncthreads();
+  unsigned off = 0, tot = 0;
+#pragma unroll
+  for (int j = 0; j < kSortThreads / 64; ++j) {
+    const unsigned w = wsum[j];
+    off += j < wv ? w : 0u;
+    tot += w;
   }
-  unsigned run = threadIdx.x ? sums[threadIdx.x - 1] : 0u;
-  for (int i = a; i < b; ++i) {
-    const unsigned v = hist[i];
-    hist[i] = run;
-    run += v;
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+__global__ __launch_bounds__(kSortThreads) void radix_scan_kernel(
+    unsigned *__restrict__ hist, int nblk, unsigned *__restrict__ dtot) {
+  __shared__ unsigned wsum[kSortThreads / 64];
+  unsigned *h = hist + (size_t)blockIdx.x * nblk;
+  unsigned carry = 0;
+  for (int base = 0; base < nblk; base += kSortThreads * kScanPer) {
+    const int a = base + threadIdx.x * kScanPer;
+    unsigned v[kScanPer];
+    unsigned s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      v[j] = (a + j < nblk) ? h[a + j] : 0u;
+      s += v[j];
+    }
+    unsigned tot = 0;
+    unsigned run = carry + block_exclusive_scan256(s, wsum, &tot);
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      if (a + j < nblk) h[a + j] = run;
+      run += v[j];
+    }
+    carry += tot;
   }
+  if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
 // Stable scatter of one block's chunk by the digit at `shift`.  Items are
@@ -168,12 +204,16 @@ __global__ __launch_bounds__(kScanThreads) void radix_scan_kernel(unsigned *hist
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const unsigned *__restrict__ kin, const unsigned *__restrict__ vin,
     int64_t npad, int shift, const unsigned *__restrict__ off, int nblk,
-    unsigned *__restrict__ kout, unsigned *__restrict__ vout) {
+    const unsigned *__restrict__ dtot, unsigned *__restrict__ kout,
+    unsigned *__restrict__ vout) {
   constexpr int W = kSortThreads / 64;
   __shared__ unsigned run[256];
   __shared__ unsigned wc[W][256];
+  __shared__ unsigned wsum[W];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  run[tid] = off[(size_t)tid * nblk + blockIdx.x];
+  unsigned all = 0;
+  const unsigned dstart = block_exclusive_scan256(dtot[tid], wsum, &all);
+  run[tid] = dstart + off[(size_t)tid * nblk + blockIdx.x];
   for (int v = 0; v < W; ++v) wc[v][tid] = 0u;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
