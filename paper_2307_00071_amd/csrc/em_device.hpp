@@ -92,6 +92,40 @@ __device__ inline void tri_inv3(const double *L, double *P) {
   P[0] = p00; P[1] = p10; P[2] = p11; P[3] = p20; P[4] = p21; P[5] = p22;
 }
 
+// Cholesky of the SPD 3x3 C and P = L^-1 together: the three diagonal
+// reciprocals serve both (3 square roots, 3 divisions).  Returns false on a
+// non-positive or non-finite pivot.
+__device__ __forceinline__ bool chol_inv3(const double *C, double *P) {
+  double a = C[0];
+  if (!(a > 0.0) || !isfinite(a)) return false;
+  const double l00 = sqrt(a), r0 = 1.0 / l00;
+  const double l10 = C[1] * r0, l20 = C[3] * r0;
+  const double b = C[2] - l10 * l10;
+  if (!(b > 0.0) || !isfinite(b)) return false;
+  const double l11 = sqrt(b), r1 = 1.0 / l11;
+  const double l21 = (C[4] - l20 * l10) * r1;
+  const double c = C[5] - l20 * l20 - l21 * l21;
+  if (!(c > 0.0) || !isfinite(c)) return false;
+  const double r2 = 1.0 / sqrt(c);
+  const double p10 = -l10 * r0 * r1;
+  P[0] = r0; P[1] = p10; P[2] = r1;
+  P[3] = -(l20 * r0 + l21 * p10) * r2; P[4] = -l21 * r1 * r2; P[5] = r2;
+  return true;
+}
+
+// The E-step block of one component (all but [3]) from mu and P.
+__device__ __forceinline__ void store_eblock(float *q, const double *mu, const double *P) {
+  const double s = sqrt(0.5 * kLog2e);
+  double fro = 0.0;
+  q[0] = (float)mu[0]; q[1] = (float)mu[1]; q[2] = (float)mu[2];
+  for (int j = 0; j < 6; ++j) {
+    q[4 + j] = (float)(s * P[j]);
+    fro += P[j] * P[j];
+  }
+  // |P'|_F rounded up: the tile-culling bound needs an upper bound of |P'|_2
+  q[10] = (float)(s * sqrt(fro) * (1.0 + 1e-6));
+}
+
 // Stores one component (pi, mu, Sigma) in the FP64 state, its E-step block
 // (all but [3]) and its shift; returns c_b * log2(e), or -inf when Sigma is
 // not SPD (the component then contributes 2^-inf = 0 everywhere).
@@ -108,23 +142,15 @@ __device__ inline double component_terms(int b, double pi, const double *mu,
   shift[b] = make_float4(mf0, mf1, mf2, 0.0f);
   float *q = cpar + (size_t)b * kParStride;
   q[0] = mf0; q[1] = mf1; q[2] = mf2;
-  double L[6], P[6];
-  if (!chol3(C, L)) {
+  double P[6];
+  if (!chol_inv3(C, P)) {
     for (int j = 0; j < 6; ++j) q[4 + j] = 0.0f;
     q[10] = 0.0f;
     return -INFINITY;
   }
-  tri_inv3(L, P);
+  store_eblock(q, mu, P);
   // ln pi + sum_j ln P_jj = ln(pi P00 P11 P22), one logarithm
   const double c = log(pi * P[0] * P[2] * P[5]) - 1.5 * kLn2Pi;
-  const double s = sqrt(0.5 * kLog2e);
-  double fro = 0.0;
-  for (int j = 0; j < 6; ++j) {
-    q[4 + j] = (float)(s * P[j]);
-    fro += P[j] * P[j];
-  }
-  // |P'|_F rounded up: the tile-culling bound needs an upper bound of |P'|_2
-  q[10] = (float)(s * sqrt(fro) * (1.0 + 1e-6));
   return c * kLog2e;
 }
 
@@ -211,9 +237,9 @@ __device__ inline double block_max_fast(double v, double *scratch) {
 // which is sum g (x - mu)(x - mu)^T / N_b + lambda I exactly;
 //   pi_b = N_b / sum_a N_a, then the eq. 3 terms for the next E-step.
 // One block of NT >= K threads, thread b owns component b (registers only);
-// scratch holds NT / 64 + 1 doubles.
+// scratch holds 2 NT / 64 doubles.
 template <int NT>
-__device__ void em_update_block(const double *tot, int K, int umode, double reg,
+__device__ __forceinline__ void em_update_block(const double *tot, int K, int umode, double reg,
                                 const float *cpar_in, const float4 *shift_in,
                                 float *cpar_out, float4 *shift_out,
                                 double *th64, double *scratch, uint32_t *status) {
@@ -265,16 +291,52 @@ __device__ void em_update_block(const double *tot, int K, int umode, double reg,
     }
     if (!fin) set_status(status, kStNonFinite);
   }
-  const double Ntot = block_sum_fast<NT>(Nb, scratch);
-  double c = -INFINITY;
-  if (act) {
-    c = component_terms(b, Nb / Ntot, mu, C, Nb, cpar_out, shift_out, th64);
-    if (!isfinite(c)) set_status(status, kStNotSpd);
+  // Cholesky, P and cb = ln(N_b P00 P11 P22) before any reduction: with
+  // pi_b = N_b / N, c_b = cb - ln N - 3/2 ln 2pi, so c_b - max_a c_a =
+  // cb - max_a cb_a and one combined reduction (sum N_b, max cb) suffices.
+  double P[6] = {0, 0, 0, 0, 0, 0};
+  double cb = -INFINITY;
+  if (act && chol_inv3(C, P)) cb = log(Nb * P[0] * P[2] * P[5]);
+  if (act && !isfinite(cb)) set_status(status, kStNotSpd);
+  double sN = act ? Nb : 0.0, mC = cb;
+  for (int off = 32; off > 0; off >>= 1) {
+    sN += __shfl_xor(sN, off, 64);
+    mC = fmax(mC, __shfl_xor(mC, off, 64));
   }
-  double Cmax = block_max_fast<NT>(c, scratch);
-  if (!isfinite(Cmax)) Cmax = 0.0;
-  if (act) cpar_out[(size_t)b * kParStride + 3] = isfinite(c) ? (float)(c - Cmax) : -INFINITY;
-  if (b == 0) *reinterpret_cast<double *>(cpar_out + (size_t)K * kParStride) = Cmax;
+  constexpr int NWV = NT / 64;
+  if ((b & 63) == 0) {
+    scratch[b >> 6] = sN;
+    scratch[NWV + (b >> 6)] = mC;
+  }
+  __syncthreads();
+  double Ntot = scratch[0], Mx = scratch[NWV];
+#pragma unroll
+  for (int j = 1; j < NWV; ++j) {
+    Ntot += scratch[j];
+    Mx = fmax(Mx, scratch[NWV + j]);
+  }
+  if (act) {
+    double *t = th64 + (size_t)b * kTh64Stride;
+    t[0] = Nb / Ntot;
+    for (int j = 0; j < 3; ++j) t[1 + j] = mu[j];
+    for (int j = 0; j < 6; ++j) t[4 + j] = C[j];
+    t[10] = Nb;
+    shift_out[b] = make_float4((float)mu[0], (float)mu[1], (float)mu[2], 0.0f);
+    float *q = cpar_out + (size_t)b * kParStride;
+    if (isfinite(cb)) {
+      store_eblock(q, mu, P);
+      q[3] = (float)((cb - Mx) * kLog2e);
+    } else {
+      q[0] = (float)mu[0]; q[1] = (float)mu[1]; q[2] = (float)mu[2];
+      for (int j = 0; j < 6; ++j) q[4 + j] = 0.0f;
+      q[10] = 0.0f;
+      q[3] = -INFINITY;
+    }
+  }
+  if (b == 0) {
+    const double Cmax = isfinite(Mx) ? (Mx - log(Ntot) - 1.5 * kLn2Pi) * kLog2e : 0.0;
+    *reinterpret_cast<double *>(cpar_out + (size_t)K * kParStride) = Cmax;
+  }
 }
 
 // Caller-supplied theta_0 (FP32 w, mu, cov) -> FP64 state and E-step block;
@@ -1117,7 +1179,7 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
 //  reduce_rows_kernel  red2[y][c] = sum of part[r][c] over the y-th chunk of
 //                      rows; a block owns 64 columns x one chunk, its 4
 //                      waves take interleaved rows and are added in wave
-//                      order (loads issued 4 at a time, adds in row order).
+//                      order (up to 16 loads in flight, adds in row order).
 //  update_kernel       one block: tot[c] = sum_y red2[y][c] in y order, then
 //                      the M-step (em_update_block) from LDS.
 constexpr int kRedChunks = 16;
@@ -1133,15 +1195,17 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(
   const int r0 = blockIdx.y * cs, r1 = min(nrows, r0 + cs);
   double s = 0.0;
   if (c < ncols) {
-    int r = r0 + wv;
-    for (; r + 12 < r1; r += 16) {
-      const double v0 = part[(size_t)r * ncols + c];
-      const double v1 = part[(size_t)(r + 4) * ncols + c];
-      const double v2 = part[(size_t)(r + 8) * ncols + c];
-      const double v3 = part[(size_t)(r + 12) * ncols + c];
-      s += v0; s += v1; s += v2; s += v3;
+    // the wave's rows r0 + wv + 4 i: up to 16 loads in flight, added in order
+    for (int base = r0 + wv; base < r1; base += 64) {
+      double v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int r = base + 4 * i;
+        v[i] = r < r1 ? part[(size_t)r * ncols + c] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) s += v[i];
     }
-    for (; r < r1; r += 4) s += part[(size_t)r * ncols + c];
   }
   sh[wv][lane] = s;
   __syncthreads();
@@ -1171,7 +1235,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdPtrs q, UpdArgs 
   const int tid = threadIdx.x;
   const int K = a.K;
   double *tot = reinterpret_cast<double *>(smem);  // ncols
-  double *scratch = tot + a.ncols;                 // kUpdThreads / 64 + 1
+  double *scratch = tot + a.ncols;                 // 2 kUpdThreads / 64 + 2
   for (int c = a.col0 + tid; c < a.ncols; c += kUpdThreads) {
     double t = 0.0;
 #pragma unroll
@@ -1205,7 +1269,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdPtrs q, UpdArgs 
 }
 
 inline size_t update_lds_bytes(int K) {
-  return ((size_t)kNStat * K + 1 + kUpdThreads / 64 + 2) * sizeof(double);
+  return ((size_t)kNStat * K + 1 + 2 * (kUpdThreads / 64) + 2) * sizeof(double);
 }
 
 
