@@ -892,46 +892,53 @@ __device__ __forceinline__ uint64_t cull_ballot(const float4 *cp, float4 sp) {
 #ifndef GMM_CULL_WPE
 #define GMM_CULL_WPE 1
 #endif
+
+// LDS of the culled tile loop (carved from the dynamic shared memory).
+struct CullLds {
+  float *E;          // SCAP rows of RS
+  float4 *Xs;        // XS
+  float4 *ShL;       // K shifts
+  float4 *CP;        // cull parameters, 3 float4 per component, 64-padded
+  double *acc;       // K x 10 FP64 sums
+  uint64_t *masks;   // 16
+  uint64_t *fbmask;  // W
+  double *wL;        // NW
+  float2 *fbv;       // T
+  float *reds;       // R x T
+  int *list;         // K
+  int *nact_s;       // 1
+};
+
 template <int BLOCK, int T, int TRIP, int SCAP>
-__global__ __launch_bounds__(BLOCK)
-__attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
-    const float4 *__restrict__ pts,    // staged (x, y, z, tag), ntiles * T
-    const float4 *__restrict__ sph,    // ntiles bounding spheres
-    const float *__restrict__ cpar,    // K x 16 floats, then the bound C
-    const float4 *__restrict__ shift,  // K
-    double *__restrict__ part,         // grid rows of ncols
-    float *__restrict__ lse_out,       // N or NULL
-    TileArgs a) {
+__device__ __forceinline__ CullLds cull_carve(unsigned char *smem, int K) {
   using S = CullShape<BLOCK, T, TRIP, SCAP>;
-  constexpr int NW = S::NW, W = S::W, R = S::R, P = S::P, RS = S::RS;
-  constexpr int SLOTS = BLOCK / P;  // slots per M round
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int K = a.K, mode = a.mode, ntiles = a.ntiles;
   const int nchk = (K + 63) >> 6;
-  float *E = reinterpret_cast<float *>(smem);
-  float4 *Xs = reinterpret_cast<float4 *>(
-      smem + (((size_t)SCAP * RS * sizeof(float) + 15) & ~(size_t)15));
-  float4 *ShL = Xs + S::XS;
-  float4 *CP = ShL + K;                                    // [nchk * 64][3]
-  double *acc = reinterpret_cast<double *>(CP + (size_t)nchk * 64 * 3);
-  uint64_t *masks = reinterpret_cast<uint64_t *>(acc + (size_t)K * kNStat);  // [16]
-  uint64_t *fbmask = masks + 16;                                             // [W]
-  double *wL = reinterpret_cast<double *>(fbmask + W);
-  float2 *fbv = reinterpret_cast<float2 *>(wL + NW);
-  float *reds = reinterpret_cast<float *>(fbv + T);                          // [R][T]
-  int *list = reinterpret_cast<int *>(reds + R * T);
-  int *nact_s = list + K;
+  CullLds L;
+  L.E = reinterpret_cast<float *>(smem);
+  L.Xs = reinterpret_cast<float4 *>(
+      smem + (((size_t)SCAP * S::RS * sizeof(float) + 15) & ~(size_t)15));
+  L.ShL = L.Xs + S::XS;
+  L.CP = L.ShL + K;
+  L.acc = reinterpret_cast<double *>(L.CP + (size_t)nchk * 64 * 3);
+  L.masks = reinterpret_cast<uint64_t *>(L.acc + (size_t)K * kNStat);
+  L.fbmask = L.masks + 16;
+  L.wL = reinterpret_cast<double *>(L.fbmask + S::W);
+  L.fbv = reinterpret_cast<float2 *>(L.wL + S::NW);
+  L.reds = reinterpret_cast<float *>(L.fbv + T);
+  L.list = reinterpret_cast<int *>(L.reds + S::R * T);
+  L.nact_s = L.list + K;
+  return L;
+}
 
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int pg = w % W, rr = w / W;
-  const int t = pg * 64 + lane;     // this lane's point in a tile
-  const int tx = t + t / TRIP;      // its column in Xs and the E rows
-  const double Cb = *reinterpret_cast<const double *>(cpar + (size_t)K * kParStride);
-
+// Per frame: shifts, cull parameters and zero sums into LDS.
+template <int BLOCK>
+__device__ __forceinline__ void cull_begin(const CullLds &L, const float *__restrict__ cpar,
+                                           const float4 *__restrict__ shift, int K) {
+  const int tid = threadIdx.x;
+  const int nchk = (K + 63) >> 6;
   for (int b = tid; b < K; b += BLOCK) {
-    ShL[b] = shift[b];
-    for (int j = 0; j < kNStat; ++j) acc[(size_t)b * kNStat + j] = 0.0;
+    L.ShL[b] = shift[b];
+    for (int j = 0; j < kNStat; ++j) L.acc[(size_t)b * kNStat + j] = 0.0;
   }
   for (int c = tid; c < nchk * 64; c += BLOCK) {
     float4 u = make_float4(0.f, 0.f, 0.f, -INFINITY), v = make_float4(0.f, 0.f, 0.f, 0.f),
@@ -942,15 +949,43 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
       v = make_float4(q[4], q[5], q[6], q[7]);
       z = make_float4(q[8], q[9], q[10], 0.f);
     }
-    CP[3 * c] = u;
-    CP[3 * c + 1] = v;
-    CP[3 * c + 2] = z;
+    L.CP[3 * c] = u;
+    L.CP[3 * c + 1] = v;
+    L.CP[3 * c + 2] = z;
   }
-  double Lacc = 0.0;
-  unsigned long long npairs = 0;
-  const int grid = gridDim.x;
-  int tile = blockIdx.x;
   __syncthreads();
+}
+
+// The tiles first, first + stride, ... < end of one frame: cull, E-phase,
+// normaliser, M-phase into L.acc; lse sums into Lacc, active pairs into
+// npairs (thread 0).
+template <int BLOCK, int T, int TRIP, int SCAP>
+__device__ __forceinline__ void cull_tiles(
+    const CullLds &L, const float4 *__restrict__ pts, const float4 *__restrict__ sph,
+    const float *__restrict__ cpar, int K, int mode, int first, int end, int stride,
+    float *__restrict__ lse_out, double &Lacc, unsigned long long &npairs) {
+  using S = CullShape<BLOCK, T, TRIP, SCAP>;
+  constexpr int NW = S::NW, W = S::W, R = S::R, P = S::P, RS = S::RS;
+  constexpr int SLOTS = BLOCK / P;  // slots per M round
+  const int nchk = (K + 63) >> 6;
+  float *E = L.E;
+  float4 *Xs = L.Xs;
+  const float4 *ShL = L.ShL;
+  const float4 *CP = L.CP;
+  double *acc = L.acc;
+  uint64_t *masks = L.masks;
+  uint64_t *fbmask = L.fbmask;
+  float2 *fbv = L.fbv;
+  float *reds = L.reds;
+  int *list = L.list;
+  int *nact_s = L.nact_s;
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int pg = w % W, rr = w / W;
+  const int t = pg * 64 + lane;     // this lane's point in a tile
+  const int tx = t + t / TRIP;      // its column in Xs and the E rows
+  const double Cb = *reinterpret_cast<const double *>(cpar + (size_t)K * kParStride);
 
   // active list of a tile from the masks: wave w < nchk places chunk w
   auto build_list = [&]() {
@@ -966,23 +1001,24 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
   };
 
   // first tile: masks, list; the point and sphere of the next tile ahead
+  int tile = first;
   float4 xn = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
   float4 spn = make_float4(0.f, 0.f, 0.f, -1.0f);
-  if (tile < ntiles) {
+  if (tile < end) {
     xn = pts[(size_t)tile * T + t];
     if (w < nchk) {
       const uint64_t m = cull_ballot(CP + 3 * ((w << 6) + lane), sph[tile]);
       if (lane == 0) masks[w] = m;
     }
-    if (tile + grid < ntiles) spn = sph[tile + grid];
+    if (tile + stride < end) spn = sph[tile + stride];
   }
   __syncthreads();
-  if (tile < ntiles) build_list();
+  if (tile < end) build_list();
   __syncthreads();
 
-  for (; tile < ntiles; tile += grid) {
+  for (; tile < end; tile += stride) {
     const float4 x = xn;
-    if (tile + grid < ntiles) xn = pts[(size_t)(tile + grid) * T + t];
+    if (tile + stride < end) xn = pts[(size_t)(tile + stride) * T + t];
     const bool valid = __float_as_int(x.w) >= 0;
     const int nact = *nact_s;
 
@@ -1115,12 +1151,12 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
       }
     }
     // ---- cull of the next tile
-    const bool more = tile + grid < ntiles;
+    const bool more = tile + stride < end;
     if (more && w < nchk) {
       const uint64_t m = cull_ballot(CP + 3 * ((w << 6) + lane), spn);
       if (lane == 0) masks[w] = m;
     }
-    if (tile + 2 * grid < ntiles) spn = sph[tile + 2 * grid];
+    if (tile + 2 * stride < end) spn = sph[tile + 2 * stride];
     __syncthreads();
 
     // ---- far points of this tile (rare): wave 0, one lane per component
@@ -1153,25 +1189,50 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
     if (more) build_list();
     __syncthreads();
   }
+}
 
-  // ---- this block's partial row
-  double *row = part + (size_t)blockIdx.x * a.ncols;
+// The FP64 sums and the lse sum of one frame into its partial row.
+template <int BLOCK>
+__device__ __forceinline__ void cull_end(const CullLds &L, double *__restrict__ row,
+                                         int K, int mode, double Lacc) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (mode != kSoftLogLik) {
     for (int i = tid; i < K * kNStat; i += BLOCK) {
       const int j = i / K, b = i - j * K;
-      row[i] = acc[(size_t)b * kNStat + j];
+      row[i] = L.acc[(size_t)b * kNStat + j];
     }
   }
   double v = Lacc;
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  if (lane == 0) wL[w] = v;
+  if (lane == 0) L.wL[w] = v;
   __syncthreads();
   if (tid == 0) {
     double sum = 0.0;
-    for (int j = 0; j < NW; ++j) sum += wL[j];
+    for (int j = 0; j < BLOCK / 64; ++j) sum += L.wL[j];
     row[kNStat * K] = sum;
-    if (a.pairs) atomicAdd(a.pairs, npairs);
   }
+  __syncthreads();  // LDS free for the next frame
+}
+
+template <int BLOCK, int T, int TRIP, int SCAP>
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
+    const float4 *__restrict__ pts,    // staged (x, y, z, tag), ntiles * T
+    const float4 *__restrict__ sph,    // ntiles bounding spheres
+    const float *__restrict__ cpar,    // K x 16 floats, then the bound C
+    const float4 *__restrict__ shift,  // K
+    double *__restrict__ part,         // grid rows of ncols
+    float *__restrict__ lse_out,       // N or NULL
+    TileArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const CullLds L = cull_carve<BLOCK, T, TRIP, SCAP>(smem, a.K);
+  cull_begin<BLOCK>(L, cpar, shift, a.K);
+  double Lacc = 0.0;
+  unsigned long long npairs = 0;
+  cull_tiles<BLOCK, T, TRIP, SCAP>(L, pts, sph, cpar, a.K, a.mode, blockIdx.x, a.ntiles,
+                                    gridDim.x, lse_out, Lacc, npairs);
+  cull_end<BLOCK>(L, part + (size_t)blockIdx.x * a.ncols, a.K, a.mode, Lacc);
+  if (threadIdx.x == 0 && a.pairs) atomicAdd(a.pairs, npairs);
 }
 
 // ------------------------------------------------------ reduction kernels
@@ -1291,11 +1352,37 @@ struct BFrame {
   int ncols;        // 10 K + 1
   int nrows;        // partial rows (segments)
   int roff;         // first column of the frame in the reduced array
-  int pad;
+  int n;            // points (the staged range is padded to 128)
 };
 struct BSeg {
   int frame, t0, t1, row;   // staged tiles [t0, t1) of one frame
 };
+
+// Batched fits: a block takes its segments (frame, tiles [t0, t1), row) in
+// order, each with that frame's components (LDS sized for the largest K).
+template <int BLOCK, int T, int TRIP, int SCAP>
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_batch_kernel(
+    const float4 *__restrict__ pts, const float4 *__restrict__ sph,
+    const float *__restrict__ cpar_all, const float4 *__restrict__ shift_all,
+    double *__restrict__ part, const BFrame *__restrict__ frames,
+    const BSeg *__restrict__ segs, const int *__restrict__ blk_seg, int mode,
+    int kmax) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const CullLds L = cull_carve<BLOCK, T, TRIP, SCAP>(smem, kmax);
+  for (int si = blk_seg[blockIdx.x]; si < blk_seg[blockIdx.x + 1]; ++si) {
+    const BSeg g = segs[si];
+    const BFrame F = frames[g.frame];
+    const float *cpar = cpar_all + F.cpoff;
+    cull_begin<BLOCK>(L, cpar, shift_all + F.koff, F.K);
+    double Lacc = 0.0;
+    unsigned long long npairs = 0;
+    cull_tiles<BLOCK, T, TRIP, SCAP>(L, pts, sph, cpar, F.K, mode, g.t0, g.t1, 1,
+                                      nullptr, Lacc, npairs);
+    cull_end<BLOCK>(L, part + F.poff + (size_t)g.row * F.ncols, F.K, mode, Lacc);
+  }
+}
+
 
 template <int BLOCK, int T, int TRIP>
 __global__ __launch_bounds__(BLOCK) void em_batch_kernel(

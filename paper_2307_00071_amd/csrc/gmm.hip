@@ -985,19 +985,38 @@ bool batch_instance(int trip, decltype(BatchClass::launch) *fn, const void **kfn
 
 // Host plan of a batched fit: frame table, per-class cost-balanced tile
 // ranges cut into per-frame segments, and the workspace layout.
+// The culled soft passes of a batched fit: one kernel instance, its own
+// cost-balanced segments over tiles of kBatchCullT points and its own frame
+// table (partial rows differ from the dense passes').
+constexpr int kBatchCullT = 128;
+constexpr int kBatchCullBlock = 512;
+struct BatchCull {
+  int grid = 0;
+  size_t lds = 0;
+  std::vector<BFrame> frames;
+  std::vector<BSeg> segs;
+  std::vector<int> blk;
+  size_t frames_off = 0, seg_off = 0, blk_off = 0;
+};
+
 struct BatchPlan {
   int B = 0, Ktot = 0, Kmax = 0, ncols_max = 0;
-  int64_t tiles = 0;
+  int64_t tiles = 0;   // staged tiles of kBatchT points (frames padded to kBatchCullT)
   std::vector<BFrame> frames;
   std::vector<BatchClass> classes;
+  bool cull = false, sort = false;
+  BatchCull cc;
   size_t plan_bytes = 0;
   // workspace offsets
   size_t status, plan, cpar[2], shift[2], th64, red, part, pts4, total;
+  size_t raw4 = 0, keys[2] = {0, 0}, vals[2] = {0, 0}, hist = 0, dtot = 0, box6 = 0,
+         tsph = 0;
+  int sort_blocks = 0;
   size_t red_len = 0, part_len = 0;
 };
 
 gmm_status make_batch_plan(int B, const int64_t *pt_off, const int32_t *k_off,
-                           BatchPlan *bp) {
+                           BatchPlan *bp, bool want_cull = false) {
   DevInfo di = dev_info();
   if (di.cus <= 0) return fail(GMM_ERR_DEVICE, "no HIP device");
   if (B <= 0) return fail(GMM_ERR_INVALID_ARG, "B=%d must be positive", B);
@@ -1021,7 +1040,8 @@ gmm_status make_batch_plan(int B, const int64_t *pt_off, const int32_t *k_off,
     F.roff = roff;
     roff += F.ncols;
     F.toff = toff;
-    toff += (n + kBatchT - 1) / kBatchT;
+    F.n = (int)n;
+    toff += (n + kBatchCullT - 1) / kBatchCullT * (kBatchCullT / kBatchT);
     bp->Kmax = std::max(bp->Kmax, K);
     bp->ncols_max = std::max(bp->ncols_max, F.ncols);
   }
@@ -1096,6 +1116,67 @@ gmm_status make_batch_plan(int B, const int64_t *pt_off, const int32_t *k_off,
     poff += (int64_t)nrows[f] * bp->frames[f].ncols;
   }
   bp->part_len = poff;
+  // culled soft passes: segments over tiles of kBatchCullT points
+  bp->cull = want_cull && B <= 256 && bp->Kmax <= kBatchCullBlock;
+  if (bp->cull) {
+    BatchCull &cc = bp->cc;
+    using Kern = decltype(&em_cull_batch_kernel<kBatchCullBlock, kBatchCullT, 8, 32>);
+    const Kern kfn = &em_cull_batch_kernel<kBatchCullBlock, kBatchCullT, 8, 32>;
+    cc.lds = cull_lds_bytes<kBatchCullBlock, kBatchCullT, 8, 32>(bp->Kmax);
+    int per_cu = 0;
+    if (cc.lds > (di.lds_max ? di.lds_max : 65536) ||
+        (cc.lds > 65536 &&
+         hipFuncSetAttribute(reinterpret_cast<const void *>(kfn),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)cc.lds) != hipSuccess) ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kfn),
+                                                     kBatchCullBlock, cc.lds) != hipSuccess ||
+        per_cu <= 0) {
+      bp->cull = false;
+    } else {
+      const int r = kBatchCullT / kBatchT;
+      int64_t ctiles = 0;
+      double cost = 0.0;
+      for (int f = 0; f < B; ++f) {
+        const int64_t nt = (bp->frames[f].n + kBatchCullT - 1) / kBatchCullT;
+        ctiles += nt;
+        cost += (double)nt * bp->frames[f].K;
+      }
+      cc.grid = (int)std::min<int64_t>(ctiles, (int64_t)di.cus * per_cu);
+      const double target = cost / cc.grid;
+      double acc = 0.0;
+      int blk = 0;
+      std::vector<int> cn(B, 0);
+      cc.blk.push_back(0);
+      for (int f = 0; f < B; ++f) {
+        const BFrame &F = bp->frames[f];
+        const int64_t nt = (F.n + kBatchCullT - 1) / kBatchCullT;
+        const int64_t t0 = F.toff / r;
+        int64_t t = 0;
+        while (t < nt) {
+          const double room = (blk + 1) * target - acc;
+          int64_t take = (int64_t)std::ceil(room / F.K - 1e-9);
+          if (blk == cc.grid - 1) take = nt - t;
+          take = std::max<int64_t>(1, std::min<int64_t>(take, nt - t));
+          cc.segs.push_back(BSeg{f, (int)(t0 + t), (int)(t0 + t + take), cn[f]++});
+          t += take;
+          acc += (double)take * F.K;
+          if (acc >= (blk + 1) * target - 1e-6 && blk < cc.grid - 1) {
+            ++blk;
+            cc.blk.push_back((int)cc.segs.size());
+          }
+        }
+      }
+      while ((int)cc.blk.size() < cc.grid + 1) cc.blk.push_back((int)cc.segs.size());
+      cc.frames = bp->frames;
+      int64_t cpo = 0;
+      for (int f = 0; f < B; ++f) {
+        cc.frames[f].nrows = cn[f];
+        cc.frames[f].poff = cpo;
+        cpo += (int64_t)cn[f] * cc.frames[f].ncols;
+      }
+      bp->part_len = std::max<int64_t>(bp->part_len, cpo);
+    }
+  }
   // plan upload layout
   size_t o = align256(sizeof(BFrame) * B);
   for (auto &c : bp->classes) {
@@ -1103,6 +1184,14 @@ gmm_status make_batch_plan(int B, const int64_t *pt_off, const int32_t *k_off,
     o = align256(o + sizeof(BSeg) * c.segs.size());
     c.blk_off = o;
     o = align256(o + sizeof(int) * c.blk.size());
+  }
+  if (bp->cull) {
+    bp->cc.frames_off = o;
+    o = align256(o + sizeof(BFrame) * B);
+    bp->cc.seg_off = o;
+    o = align256(o + sizeof(BSeg) * bp->cc.segs.size());
+    bp->cc.blk_off = o;
+    o = align256(o + sizeof(int) * bp->cc.blk.size());
   }
   bp->plan_bytes = o;
   // workspace
@@ -1118,7 +1207,68 @@ gmm_status make_batch_plan(int B, const int64_t *pt_off, const int32_t *k_off,
   bp->red = o; o = align256(o + bp->red_len * sizeof(double));
   bp->part = o; o = align256(o + bp->part_len * sizeof(double));
   bp->pts4 = o; o = align256(o + (size_t)bp->tiles * kBatchT * sizeof(float4));
+  if (bp->cull) {
+    const size_t np = (size_t)bp->tiles * kBatchT;
+    bp->tsph = o; o = align256(o + np / kBatchCullT * sizeof(float4));
+    bp->sort = true;
+    bp->sort_blocks = (int)((np + kSortChunk - 1) / kSortChunk);
+    bp->raw4 = o; o = align256(o + np * sizeof(float4));
+    for (int i = 0; i < 2; ++i) {
+      bp->keys[i] = o; o = align256(o + np * sizeof(unsigned));
+      bp->vals[i] = o; o = align256(o + np * sizeof(unsigned));
+    }
+    bp->hist = o; o = align256(o + (size_t)256 * bp->sort_blocks * sizeof(unsigned));
+    bp->dtot = o; o = align256(o + 256 * sizeof(unsigned));
+    bp->box6 = o; o = align256(o + (size_t)B * 6 * sizeof(float));
+  }
   bp->total = o;
+  return GMM_OK;
+}
+
+// Culled batched passes only with GMM_BATCH_CULL=1 (and not GMM_CULL=0):
+// on subsampled frames a 128-point tile spans a large area, culling removes
+// little and the dense batch kernel is faster (64 frames of 20k..300k
+// depth points, T = 20: 30 ms dense, 40 ms culled).
+bool batch_cull_wanted() {
+  const char *off = getenv("GMM_CULL");
+  if (off && off[0] == '0') return false;
+  const char *on = getenv("GMM_BATCH_CULL");
+  return on && on[0] == '1';
+}
+
+// Every frame of the staged batch in its own Morton order: raw4 -> pts4.
+gmm_status batch_spatial_order(const BatchPlan &bp, void *ws, hipStream_t s) {
+  const int64_t np = bp.tiles * kBatchT;
+  const int nblk = bp.sort_blocks;
+  const BFrame *frames = reinterpret_cast<const BFrame *>(at<unsigned char>(ws, bp.plan));
+  hipLaunchKernelGGL(frame_box_kernel, dim3(bp.B), dim3(kSortThreads), 0, s,
+                     at<float4>(ws, bp.raw4), frames, kBatchT, at<float>(ws, bp.box6));
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(morton_frames_kernel, dim3(64, bp.B), dim3(kSortThreads), 0, s,
+                     at<float4>(ws, bp.raw4), frames, kBatchT, kBatchCullT,
+                     at<float>(ws, bp.box6), at<unsigned>(ws, bp.keys[0]),
+                     at<unsigned>(ws, bp.vals[0]));
+  HIP_TRY(hipGetLastError());
+  int src = 0;
+  for (int shift = 0; shift < 32; shift += 8, src = 1 - src) {
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kSortThreads), 0, s,
+                       at<unsigned>(ws, bp.keys[src]), np, shift,
+                       at<unsigned>(ws, bp.hist), nblk);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(kSortThreads), 0, s,
+                       at<unsigned>(ws, bp.hist), nblk, at<unsigned>(ws, bp.dtot));
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, s,
+                       at<unsigned>(ws, bp.keys[src]), at<unsigned>(ws, bp.vals[src]),
+                       np, shift, at<unsigned>(ws, bp.hist), nblk,
+                       at<unsigned>(ws, bp.dtot), at<unsigned>(ws, bp.keys[1 - src]),
+                       at<unsigned>(ws, bp.vals[1 - src]));
+    HIP_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((np + kSortThreads - 1) / kSortThreads)),
+                     dim3(kSortThreads), 0, s, at<float4>(ws, bp.raw4),
+                     at<unsigned>(ws, bp.vals[src]), np, at<float4>(ws, bp.pts4));
+  HIP_TRY(hipGetLastError());
   return GMM_OK;
 }
 
@@ -1135,13 +1285,25 @@ gmm_status batch_pass(BatchRun &r, int mode, int umode, double reg,
                       float *out_cov = nullptr) {
   const BatchPlan &bp = *r.bp;
   unsigned char *plan = at<unsigned char>(r.ws, bp.plan);
-  const BFrame *frames = reinterpret_cast<const BFrame *>(plan);
-  for (const auto &c : bp.classes) {
-    c.launch(c, r.s, at<float4>(r.ws, bp.pts4), at<float>(r.ws, bp.cpar[r.cur]),
-             at<float4>(r.ws, bp.shift[r.cur]), at<double>(r.ws, bp.part), frames,
-             reinterpret_cast<const BSeg *>(plan + c.seg_off),
-             reinterpret_cast<const int *>(plan + c.blk_off), mode);
+  const bool cull = bp.cull && mode != kLabels;
+  const BFrame *frames = reinterpret_cast<const BFrame *>(plan + (cull ? bp.cc.frames_off : 0));
+  if (cull) {
+    hipLaunchKernelGGL((em_cull_batch_kernel<kBatchCullBlock, kBatchCullT, 8, 32>),
+                       dim3(bp.cc.grid), dim3(kBatchCullBlock), bp.cc.lds, r.s,
+                       at<float4>(r.ws, bp.pts4), at<float4>(r.ws, bp.tsph),
+                       at<float>(r.ws, bp.cpar[r.cur]), at<float4>(r.ws, bp.shift[r.cur]),
+                       at<double>(r.ws, bp.part), frames,
+                       reinterpret_cast<const BSeg *>(plan + bp.cc.seg_off),
+                       reinterpret_cast<const int *>(plan + bp.cc.blk_off), mode, bp.Kmax);
     HIP_TRY(hipGetLastError());
+  } else {
+    for (const auto &c : bp.classes) {
+      c.launch(c, r.s, at<float4>(r.ws, bp.pts4), at<float>(r.ws, bp.cpar[r.cur]),
+               at<float4>(r.ws, bp.shift[r.cur]), at<double>(r.ws, bp.part), frames,
+               reinterpret_cast<const BSeg *>(plan + c.seg_off),
+               reinterpret_cast<const int *>(plan + c.blk_off), mode);
+      HIP_TRY(hipGetLastError());
+    }
   }
   const int only_L = mode == kSoftLogLik;
   const int ncx = (only_L ? 1 : (bp.ncols_max + 63) / 64);
@@ -1343,7 +1505,7 @@ size_t gmm_fit_batched_workspace_size(int32_t B, const int64_t *pt_off,
   g_err[0] = 0;
   if (!pt_off || !k_off) return 0;
   BatchPlan bp;
-  if (make_batch_plan(B, pt_off, k_off, &bp) != GMM_OK) return 0;
+  if (make_batch_plan(B, pt_off, k_off, &bp, batch_cull_wanted()) != GMM_OK) return 0;
   return bp.total;
 }
 
@@ -1365,7 +1527,7 @@ gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
   if (pt_off[0] != 0 || k_off[0] != 0)
     return fail(GMM_ERR_INVALID_ARG, "offsets must start at 0");
   BatchPlan bp;
-  gmm_status st = make_batch_plan(B, pt_off, k_off, &bp);
+  gmm_status st = make_batch_plan(B, pt_off, k_off, &bp, batch_cull_wanted());
   if (st != GMM_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   WsGuard guard;
@@ -1377,6 +1539,11 @@ gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
     memcpy(host.data() + c.seg_off, c.segs.data(), sizeof(BSeg) * c.segs.size());
     memcpy(host.data() + c.blk_off, c.blk.data(), sizeof(int) * c.blk.size());
   }
+  if (bp.cull) {
+    memcpy(host.data() + bp.cc.frames_off, bp.cc.frames.data(), sizeof(BFrame) * B);
+    memcpy(host.data() + bp.cc.seg_off, bp.cc.segs.data(), sizeof(BSeg) * bp.cc.segs.size());
+    memcpy(host.data() + bp.cc.blk_off, bp.cc.blk.data(), sizeof(int) * bp.cc.blk.size());
+  }
   HIP_TRY(hipMemcpyAsync(at<unsigned char>(ws, bp.plan), host.data(),
                          bp.plan_bytes, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1384,16 +1551,24 @@ gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
                      at<uint32_t>(ws, bp.status), nullptr, 0,
                      init_labels ? at<float4>(ws, bp.shift[0]) : nullptr, bp.Ktot);
   HIP_TRY(hipGetLastError());
-  // stage every frame into its tiles
+  // stage every frame into its tiles (padded to kBatchCullT points)
+  const size_t stage_to = bp.sort ? bp.raw4 : bp.pts4;
   for (int f = 0; f < B; ++f) {
     const int64_t n = pt_off[f + 1] - pt_off[f];
-    const int64_t npad = ((n + kBatchT - 1) / kBatchT) * kBatchT;
+    const int64_t npad = ((n + kBatchCullT - 1) / kBatchCullT) * kBatchCullT;
     hipLaunchKernelGGL(stage_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256),
                        0, s, pts + 3 * pt_off[f], n, npad,
                        init_labels ? init_labels + pt_off[f] : nullptr,
                        bp.frames[f].K, nullptr,
-                       at<float4>(ws, bp.pts4) + bp.frames[f].toff * kBatchT,
+                       at<float4>(ws, stage_to) + bp.frames[f].toff * kBatchT,
                        at<uint32_t>(ws, bp.status));
+    HIP_TRY(hipGetLastError());
+  }
+  if (bp.sort && (st = batch_spatial_order(bp, ws, s)) != GMM_OK) return st;
+  if (bp.cull) {
+    const int64_t nt = bp.tiles * kBatchT / kBatchCullT;
+    hipLaunchKernelGGL(tile_sphere_kernel, dim3((unsigned)nt), dim3(256), 0, s,
+                       at<float4>(ws, bp.pts4), kBatchCullT, at<float4>(ws, bp.tsph));
     HIP_TRY(hipGetLastError());
   }
   BatchRun r;

@@ -250,6 +250,58 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   }
 }
 
+// ---- batched fits: every frame in its own Morton order, frames kept in
+// place.  Keys are (frame << 24) | Morton code in the frame's own box, so a
+// four-pass sort of all staged points leaves each frame's range where it
+// was (its padding, key (frame << 24) | 0xFFFFFF, at its end).
+// (BFrame: the batched frame table of em_device.hpp, included first.)
+// One block per frame: box6[f] = (lo, hi) of the frame's points.
+__global__ __launch_bounds__(kSortThreads) void frame_box_kernel(
+    const float4 *__restrict__ pts, const BFrame *__restrict__ frames, int tpts,
+    float *__restrict__ box6) {
+  __shared__ float sh[kSortThreads / 64 * 6];
+  const BFrame F = frames[blockIdx.x];
+  const float4 *p = pts + F.toff * tpts;
+  float lo[3] = {INFINITY, INFINITY, INFINITY};
+  float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int i = threadIdx.x; i < F.n; i += kSortThreads) box_update(p[i], lo, hi);
+  box_block_reduce(lo, hi, sh);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 3; ++j) {
+      box6[blockIdx.x * 6 + j] = lo[j];
+      box6[blockIdx.x * 6 + 3 + j] = hi[j];
+    }
+}
+
+// Keys of frame blockIdx.y over its staged range of fpad points (a
+// multiple of the culled tile), starting at tile toff of tpts points.
+__global__ __launch_bounds__(kSortThreads) void morton_frames_kernel(
+    const float4 *__restrict__ pts, const BFrame *__restrict__ frames, int tpts,
+    int pad_to, const float *__restrict__ box6, unsigned *__restrict__ keys,
+    unsigned *__restrict__ vals) {
+  const int f = blockIdx.y;
+  const BFrame F = frames[f];
+  const float l0 = box6[f * 6], l1 = box6[f * 6 + 1], l2 = box6[f * 6 + 2];
+  const float ext = fmaxf(fmaxf(box6[f * 6 + 3] - l0, box6[f * 6 + 4] - l1),
+                          box6[f * 6 + 5] - l2);
+  const float sc = (ext > 0.0f && ext < INFINITY) ? 255.99f / ext : 0.0f;
+  const long long s0 = F.toff * tpts;
+  const int n = F.n, np = ((n + pad_to - 1) / pad_to) * pad_to;
+  for (int i = blockIdx.x * kSortThreads + threadIdx.x; i < np;
+       i += gridDim.x * kSortThreads) {
+    unsigned key = 0xFFFFFFu;
+    if (i < n) {
+      const float4 x = pts[s0 + i];
+      const unsigned q0 = (unsigned)fminf(fmaxf((x.x - l0) * sc, 0.0f), 255.0f);
+      const unsigned q1 = (unsigned)fminf(fmaxf((x.y - l1) * sc, 0.0f), 255.0f);
+      const unsigned q2 = (unsigned)fminf(fmaxf((x.z - l2) * sc, 0.0f), 255.0f);
+      key = spread3(q0) | (spread3(q1) << 1) | (spread3(q2) << 2);
+    }
+    keys[s0 + i] = ((unsigned)f << 24) | key;
+    vals[s0 + i] = (unsigned)(s0 + i);
+  }
+}
+
 // out[i] = in[perm[i]]
 __global__ __launch_bounds__(kSortThreads) void gather_kernel(
     const float4 *__restrict__ in, const unsigned *__restrict__ perm,

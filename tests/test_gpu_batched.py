@@ -131,3 +131,41 @@ def test_batched_deterministic_and_errors():
     with pytest.raises(_lib.GmmError):
         gmm.fit_batched(*args[:1], [600, 3, 3], iters=1,
                         labels_list=[_to(l, torch.int32) for l in labs])
+
+
+def test_batched_culled_matches_dense_batched(monkeypatch):
+    """The culled batched passes (per-frame Morton order, tiles of 128
+    points) against the dense batched kernel: same fit to FP32
+    summation-order rounding, one step within the one-step bar."""
+    print("case: batched culled vs dense", flush=True)
+    frames = _frames(9, 1200, 2000, 40000, 8, 150)
+    labs = [synth.kmeanspp_labels(X, k, 7) for X, k in frames]
+    args = ([_to(X) for X, _ in frames], [k for _, k in frames])
+    lab_t = [_to(l, torch.int32) for l in labs]
+    monkeypatch.setenv("GMM_BATCH_CULL", "1")
+    cull = gmm.fit_batched(*args, iters=10, labels_list=lab_t)
+    monkeypatch.setenv("GMM_BATCH_CULL", "0")
+    dense = gmm.fit_batched(*args, iters=10, labels_list=lab_t)
+    for (X, k), rc, rd in zip(frames, cull, dense):
+        Lc, Ld = rc.loglik.cpu().numpy(), rd.loglik.cpu().numpy()
+        assert np.abs(Lc - Ld).max() <= 1e-6 * max(np.abs(Ld).max(), X.shape[0])
+        assert _rel(rc.means.cpu().numpy(), rd.means.cpu().numpy().astype(np.float64)) <= 1e-5
+
+
+def test_batched_culled_against_oracle(monkeypatch):
+    """The culled batched passes meet the one-step bar per frame."""
+    print("case: batched culled one step", flush=True)
+    monkeypatch.setenv("GMM_BATCH_CULL", "1")
+    frames = _frames(4, 1300, 3000, 25000, 10, 120)
+    thetas = []
+    for X, k in frames:
+        lab = synth.kmeanspp_labels(X, k, 8)
+        thetas.append(tuple(a.astype(np.float32) for a in oracle.fit(X, k, 1e-3, 2, labels=lab)[:3]))
+    res = gmm.fit_batched([_to(X) for X, _ in frames], [k for _, k in frames], iters=1,
+                          theta0_list=[tuple(_to(a) for a in th) for th in thetas])
+    for (X, k), th, r in zip(frames, thetas, res):
+        wr, mur, covr, L0 = oracle.em_step(X, *(a.astype(np.float64) for a in th), 1e-3)
+        assert _rel(r.weights.cpu().numpy(), wr) <= 1e-5
+        assert _rel(r.means.cpu().numpy(), mur) <= 1e-5
+        assert _rel(r.covariances.cpu().numpy(), covr) <= 1e-5
+        assert abs(r.loglik[0].item() - L0) <= 1e-5 * max(abs(L0), X.shape[0])
