@@ -781,15 +781,18 @@ struct CullShape {
   static_assert(P * TRIP == T && (P == 8 || P == 16), "subsets");
 };
 
-// LDS of the culled kernel for K components: E rows, Xs, shifts, the cull
-// parameters, FP64 sums, masks, fallback (max, sum) per point, wL, partial
-// normalisers, the active list and its length.
-template <int BLOCK, int T, int TRIP, int SCAP>
+// LDS of the culled kernel for K components: E rows, Xs, shifts and cull
+// parameters (unless CPR: then each lane holds its component's cull
+// parameters in registers and the shifts are read from global memory),
+// FP64 sums, masks, fallback (max, sum) per point, wL, partial normalisers,
+// the active list and its length.
+template <int BLOCK, int T, int TRIP, int SCAP, bool CPR = false>
 __host__ __device__ constexpr size_t cull_lds_bytes(int K) {
   using S = CullShape<BLOCK, T, TRIP, SCAP>;
   return (((size_t)SCAP * S::RS * sizeof(float) + 15) & ~(size_t)15) +
-         (size_t)S::XS * sizeof(float4) + (size_t)K * sizeof(float4) +
-         (size_t)((K + 63) / 64) * 64 * 3 * sizeof(float4) +
+         (size_t)S::XS * sizeof(float4) +
+         (CPR ? (size_t)0 : (size_t)K * sizeof(float4)) +
+         (CPR ? (size_t)0 : (size_t)((K + 63) / 64) * 64 * 3 * sizeof(float4)) +
          (size_t)K * kNStat * sizeof(double) + 16 * sizeof(uint64_t) +
          (size_t)S::W * sizeof(uint64_t) + (size_t)S::NW * sizeof(double) +
          (size_t)T * sizeof(float2) + (size_t)S::R * T * sizeof(float) +
@@ -872,20 +875,46 @@ __device__ __forceinline__ void subset_sum(float *a) {
   }
 }
 
-// Cull test of one tile sphere against this lane's component (parameters
-// in LDS: mu, c', P' (6), |P'|_F); the wave's ballot.
+// Cull parameters of one component: (mu, c'), (P'0..3), (P'4, P'5, |P'|_F);
+// c' = -inf for a lane past the last component.
+struct CullPar {
+  float4 u, v, z;
+};
+
+__device__ __forceinline__ CullPar cull_par(const float *__restrict__ cpar, int K, int c) {
+  CullPar p;
+  p.u = make_float4(0.f, 0.f, 0.f, -INFINITY);
+  p.v = make_float4(0.f, 0.f, 0.f, 0.f);
+  p.z = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (c < K) {
+    const float *q = cpar + (size_t)c * kParStride;
+    p.u = make_float4(q[0], q[1], q[2], q[3]);
+    p.v = make_float4(q[4], q[5], q[6], q[7]);
+    p.z = make_float4(q[8], q[9], q[10], 0.f);
+  }
+  return p;
+}
+
+// Cull test of one tile sphere (radius < 0: padding only) against one
+// component.
+__device__ __forceinline__ bool cull_test(float4 u, float4 v, float4 z, float4 sp) {
+  const float d0 = sp.x - u.x, d1 = sp.y - u.y, d2 = sp.z - u.z;
+  const float z0 = v.x * d0;
+  const float z1 = fmaf(v.y, d0, v.z * d1);
+  const float z2 = fmaf(v.w, d0, fmaf(z.x, d1, z.y * d2));
+  const float dist = sqrtf(fmaf(z0, z0, fmaf(z1, z1, z2 * z2)));
+  const float bnd = fmaxf(dist - z.z * sp.w, 0.0f);
+  return fmaf(-bnd, bnd, u.w) >= kCullLog2;
+}
+
+// The wave's ballot of the cull test, this lane's component in registers
+// or (3 float4) in LDS.
+__device__ __forceinline__ uint64_t cull_ballot(const CullPar &cp, float4 sp) {
+  return __ballot(sp.w >= 0.0f && cull_test(cp.u, cp.v, cp.z, sp));
+}
 __device__ __forceinline__ uint64_t cull_ballot(const float4 *cp, float4 sp) {
   bool act = false;
-  if (sp.w >= 0.0f) {
-    const float4 u = cp[0], v = cp[1], z = cp[2];  // (mu, c'), (P'0..3), (P'4, P'5, |P'|)
-    const float d0 = sp.x - u.x, d1 = sp.y - u.y, d2 = sp.z - u.z;
-    const float z0 = v.x * d0;
-    const float z1 = fmaf(v.y, d0, v.z * d1);
-    const float z2 = fmaf(v.w, d0, fmaf(z.x, d1, z.y * d2));
-    const float dist = sqrtf(fmaf(z0, z0, fmaf(z1, z1, z2 * z2)));
-    const float bnd = fmaxf(dist - z.z * sp.w, 0.0f);
-    act = fmaf(-bnd, bnd, u.w) >= kCullLog2;
-  }
+  if (sp.w >= 0.0f) act = cull_test(cp[0], cp[1], cp[2], sp);
   return __ballot(act);
 }
 
@@ -897,7 +926,7 @@ __device__ __forceinline__ uint64_t cull_ballot(const float4 *cp, float4 sp) {
 struct CullLds {
   float *E;          // SCAP rows of RS
   float4 *Xs;        // XS
-  float4 *ShL;       // K shifts
+  float4 *ShL;       // K shifts (none if CPR)
   float4 *CP;        // cull parameters, 3 float4 per component, 64-padded
   double *acc;       // K x 10 FP64 sums
   uint64_t *masks;   // 16
@@ -909,16 +938,16 @@ struct CullLds {
   int *nact_s;       // 1
 };
 
-template <int BLOCK, int T, int TRIP, int SCAP>
+template <int BLOCK, int T, int TRIP, int SCAP, bool CPR>
 __device__ __forceinline__ CullLds cull_carve(unsigned char *smem, int K) {
   using S = CullShape<BLOCK, T, TRIP, SCAP>;
-  const int nchk = (K + 63) >> 6;
+  const int nchk = CPR ? 0 : (K + 63) >> 6;
   CullLds L;
   L.E = reinterpret_cast<float *>(smem);
   L.Xs = reinterpret_cast<float4 *>(
       smem + (((size_t)SCAP * S::RS * sizeof(float) + 15) & ~(size_t)15));
   L.ShL = L.Xs + S::XS;
-  L.CP = L.ShL + K;
+  L.CP = L.ShL + (CPR ? 0 : K);
   L.acc = reinterpret_cast<double *>(L.CP + (size_t)nchk * 64 * 3);
   L.masks = reinterpret_cast<uint64_t *>(L.acc + (size_t)K * kNStat);
   L.fbmask = L.masks + 16;
@@ -930,28 +959,24 @@ __device__ __forceinline__ CullLds cull_carve(unsigned char *smem, int K) {
   return L;
 }
 
-// Per frame: shifts, cull parameters and zero sums into LDS.
-template <int BLOCK>
+// Per frame: shifts, cull parameters (unless CPR) and zero sums into LDS.
+template <int BLOCK, bool CPR>
 __device__ __forceinline__ void cull_begin(const CullLds &L, const float *__restrict__ cpar,
                                            const float4 *__restrict__ shift, int K) {
   const int tid = threadIdx.x;
-  const int nchk = (K + 63) >> 6;
+  if (tid < 16) L.masks[tid] = 0;  // label passes OR into them
   for (int b = tid; b < K; b += BLOCK) {
-    L.ShL[b] = shift[b];
+    if (!CPR) L.ShL[b] = shift[b];
     for (int j = 0; j < kNStat; ++j) L.acc[(size_t)b * kNStat + j] = 0.0;
   }
-  for (int c = tid; c < nchk * 64; c += BLOCK) {
-    float4 u = make_float4(0.f, 0.f, 0.f, -INFINITY), v = make_float4(0.f, 0.f, 0.f, 0.f),
-           z = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (c < K) {
-      const float *q = cpar + (size_t)c * kParStride;
-      u = make_float4(q[0], q[1], q[2], q[3]);
-      v = make_float4(q[4], q[5], q[6], q[7]);
-      z = make_float4(q[8], q[9], q[10], 0.f);
+  if (!CPR) {
+    const int nchk = (K + 63) >> 6;
+    for (int c = tid; c < nchk * 64; c += BLOCK) {
+      const CullPar p = cull_par(cpar, K, c);
+      L.CP[3 * c] = p.u;
+      L.CP[3 * c + 1] = p.v;
+      L.CP[3 * c + 2] = p.z;
     }
-    L.CP[3 * c] = u;
-    L.CP[3 * c + 1] = v;
-    L.CP[3 * c + 2] = z;
   }
   __syncthreads();
 }
@@ -959,18 +984,19 @@ __device__ __forceinline__ void cull_begin(const CullLds &L, const float *__rest
 // The tiles first, first + stride, ... < end of one frame: cull, E-phase,
 // normaliser, M-phase into L.acc; lse sums into Lacc, active pairs into
 // npairs (thread 0).
-template <int BLOCK, int T, int TRIP, int SCAP>
+template <int BLOCK, int T, int TRIP, int SCAP, bool CPR, bool LAB>
 __device__ __forceinline__ void cull_tiles(
     const CullLds &L, const float4 *__restrict__ pts, const float4 *__restrict__ sph,
-    const float *__restrict__ cpar, int K, int mode, int first, int end, int stride,
-    float *__restrict__ lse_out, double &Lacc, unsigned long long &npairs) {
+    const float *__restrict__ cpar, const float4 *__restrict__ shift, int K, int mode,
+    int first, int end, int stride, float *__restrict__ lse_out, double &Lacc,
+    unsigned long long &npairs) {
   using S = CullShape<BLOCK, T, TRIP, SCAP>;
   constexpr int NW = S::NW, W = S::W, R = S::R, P = S::P, RS = S::RS;
   constexpr int SLOTS = BLOCK / P;  // slots per M round
   const int nchk = (K + 63) >> 6;
   float *E = L.E;
   float4 *Xs = L.Xs;
-  const float4 *ShL = L.ShL;
+  const float4 *ShL = CPR ? shift : L.ShL;
   const float4 *CP = L.CP;
   double *acc = L.acc;
   uint64_t *masks = L.masks;
@@ -986,6 +1012,21 @@ __device__ __forceinline__ void cull_tiles(
   const int t = pg * 64 + lane;     // this lane's point in a tile
   const int tx = t + t / TRIP;      // its column in Xs and the E rows
   const double Cb = *reinterpret_cast<const double *>(cpar + (size_t)K * kParStride);
+  // this lane's component in the cull (wave w < nchk tests chunk w)
+  const int cc = (w << 6) + lane;
+  CullPar creg;
+  if constexpr (CPR) creg = cull_par(cpar, K, cc);
+  auto cull_mask = [&](float4 sp) -> uint64_t {
+    if constexpr (CPR) return cull_ballot(creg, sp);
+    else return cull_ballot(CP + 3 * ((w << 6) + lane), sp);
+  };
+  // label passes: the components of a tile are the labels of its points
+  // (masks zero beforehand; OR is order-free, so the list is deterministic)
+  auto mark_label = [&](float4 xq) {
+    const int tg = __float_as_int(xq.w);
+    if (tg >= 0) atomicOr(reinterpret_cast<unsigned long long *>(masks + (tg >> 6)),
+                          1ull << (tg & 63));
+  };
 
   // active list of a tile from the masks: wave w < nchk places chunk w
   auto build_list = [&]() {
@@ -1006,11 +1047,15 @@ __device__ __forceinline__ void cull_tiles(
   float4 spn = make_float4(0.f, 0.f, 0.f, -1.0f);
   if (tile < end) {
     xn = pts[(size_t)tile * T + t];
-    if (w < nchk) {
-      const uint64_t m = cull_ballot(CP + 3 * ((w << 6) + lane), sph[tile]);
-      if (lane == 0) masks[w] = m;
+    if constexpr (LAB) {
+      mark_label(xn);
+    } else {
+      if (w < nchk) {
+        const uint64_t m = cull_mask(sph[tile]);
+        if (lane == 0) masks[w] = m;
+      }
+      if (tile + stride < end) spn = sph[tile + stride];
     }
-    if (tile + stride < end) spn = sph[tile + stride];
   }
   __syncthreads();
   if (tile < end) build_list();
@@ -1022,6 +1067,19 @@ __device__ __forceinline__ void cull_tiles(
     const bool valid = __float_as_int(x.w) >= 0;
     const int nact = *nact_s;
 
+    if constexpr (LAB) {
+      // ---- one-hot rows of the first SCAP slots; weight 1 per point
+      if (tid < 16) masks[tid] = 0;
+      const int tg = __float_as_int(x.w);
+      for (int sl = rr; sl < min(nact, SCAP); sl += R)
+        E[sl * RS + tx] = (__builtin_amdgcn_readfirstlane(list[sl]) == tg) ? 1.0f : 0.0f;
+      if (rr == 0) {
+        Xs[tx] = make_float4(x.x, x.y, x.z, valid ? 1.0f : 0.0f);
+        fbv[t] = make_float2(__int_as_float(tg), 0.0f);
+        if (lane == 0) fbmask[pg] = 0;
+      }
+      __syncthreads();
+    } else {
     // ---- E-phase: slots rr, rr + R, ... of the active list, four at a time
     float s = 0.0f;
     {
@@ -1093,6 +1151,7 @@ __device__ __forceinline__ void cull_tiles(
       }
     }
     __syncthreads();
+    }
 
     // ---- M-phase over the active list, SCAP slots at a time
     if (tid == 0) npairs += (unsigned)nact;
@@ -1107,9 +1166,13 @@ __device__ __forceinline__ void cull_tiles(
             const int sl = u / W, g2 = u % W;
             const int b = __builtin_amdgcn_readfirstlane(list[c0 + sl]);
             const int t2 = g2 * 64 + lane, c2 = t2 + t2 / TRIP;
-            const float4 xp = Xs[c2];
-            E[sl * RS + c2] = __builtin_amdgcn_exp2f(
-                comp_logterm(cpar + (size_t)b * kParStride, xp.x, xp.y, xp.z));
+            if constexpr (LAB) {
+              E[sl * RS + c2] = (__float_as_int(fbv[t2].x) == b) ? 1.0f : 0.0f;
+            } else {
+              const float4 xp = Xs[c2];
+              E[sl * RS + c2] = __builtin_amdgcn_exp2f(
+                  comp_logterm(cpar + (size_t)b * kParStride, xp.x, xp.y, xp.z));
+            }
           }
           __syncthreads();
         }
@@ -1152,11 +1215,15 @@ __device__ __forceinline__ void cull_tiles(
     }
     // ---- cull of the next tile
     const bool more = tile + stride < end;
-    if (more && w < nchk) {
-      const uint64_t m = cull_ballot(CP + 3 * ((w << 6) + lane), spn);
-      if (lane == 0) masks[w] = m;
+    if constexpr (LAB) {
+      if (more) mark_label(xn);
+    } else {
+      if (more && w < nchk) {
+        const uint64_t m = cull_mask(spn);
+        if (lane == 0) masks[w] = m;
+      }
+      if (tile + 2 * stride < end) spn = sph[tile + 2 * stride];
     }
-    if (tile + 2 * stride < end) spn = sph[tile + 2 * stride];
     __syncthreads();
 
     // ---- far points of this tile (rare): wave 0, one lane per component
@@ -1214,7 +1281,11 @@ __device__ __forceinline__ void cull_end(const CullLds &L, double *__restrict__ 
   __syncthreads();  // LDS free for the next frame
 }
 
-template <int BLOCK, int T, int TRIP, int SCAP>
+// One tile pass of a single frame, grid-strided over the tiles.  LAB: the
+// label pass (one-hot responsibilities from the staged labels; the active
+// list of a tile is the set of its labels), a separate instantiation so
+// that the soft passes carry none of its code.
+template <int BLOCK, int T, int TRIP, int SCAP, bool CPR, bool LAB>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
     const float4 *__restrict__ pts,    // staged (x, y, z, tag), ntiles * T
@@ -1225,12 +1296,12 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
     float *__restrict__ lse_out,       // N or NULL
     TileArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const CullLds L = cull_carve<BLOCK, T, TRIP, SCAP>(smem, a.K);
-  cull_begin<BLOCK>(L, cpar, shift, a.K);
+  const CullLds L = cull_carve<BLOCK, T, TRIP, SCAP, CPR>(smem, a.K);
+  cull_begin<BLOCK, CPR>(L, cpar, shift, a.K);
   double Lacc = 0.0;
   unsigned long long npairs = 0;
-  cull_tiles<BLOCK, T, TRIP, SCAP>(L, pts, sph, cpar, a.K, a.mode, blockIdx.x, a.ntiles,
-                                    gridDim.x, lse_out, Lacc, npairs);
+  cull_tiles<BLOCK, T, TRIP, SCAP, CPR, LAB>(L, pts, sph, cpar, shift, a.K, a.mode, blockIdx.x,
+                                         a.ntiles, gridDim.x, lse_out, Lacc, npairs);
   cull_end<BLOCK>(L, part + (size_t)blockIdx.x * a.ncols, a.K, a.mode, Lacc);
   if (threadIdx.x == 0 && a.pairs) atomicAdd(a.pairs, npairs);
 }
@@ -1369,16 +1440,16 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_batch_kernel(
     const BSeg *__restrict__ segs, const int *__restrict__ blk_seg, int mode,
     int kmax) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const CullLds L = cull_carve<BLOCK, T, TRIP, SCAP>(smem, kmax);
+  const CullLds L = cull_carve<BLOCK, T, TRIP, SCAP, false>(smem, kmax);
   for (int si = blk_seg[blockIdx.x]; si < blk_seg[blockIdx.x + 1]; ++si) {
     const BSeg g = segs[si];
     const BFrame F = frames[g.frame];
     const float *cpar = cpar_all + F.cpoff;
-    cull_begin<BLOCK>(L, cpar, shift_all + F.koff, F.K);
+    cull_begin<BLOCK, false>(L, cpar, shift_all + F.koff, F.K);
     double Lacc = 0.0;
     unsigned long long npairs = 0;
-    cull_tiles<BLOCK, T, TRIP, SCAP>(L, pts, sph, cpar, F.K, mode, g.t0, g.t1, 1,
-                                      nullptr, Lacc, npairs);
+    cull_tiles<BLOCK, T, TRIP, SCAP, false, false>(L, pts, sph, cpar, shift_all + F.koff, F.K,
+                                             mode, g.t0, g.t1, 1, nullptr, Lacc, npairs);
     cull_end<BLOCK>(L, part + F.poff + (size_t)g.row * F.ncols, F.K, mode, Lacc);
   }
 }

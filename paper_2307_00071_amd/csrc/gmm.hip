@@ -406,29 +406,36 @@ struct CullCfg {
   int block = 0, tile = 0, trip = 0, grid = 0;
   size_t lds = 0;
   const char *name = "";
-  void (*launch)(const CullCfg &, hipStream_t, const float4 *, const float4 *,
-                 const float *, const float4 *, double *, float *,
-                 const TileArgs &) = nullptr;
+  using Launch = void (*)(const CullCfg &, hipStream_t, const float4 *, const float4 *,
+                          const float *, const float4 *, double *, float *,
+                          const TileArgs &);
+  Launch launch = nullptr;      // soft passes
+  Launch launch_lab = nullptr;  // label passes
 };
 
-template <int BLOCK, int T, int TRIP, int SCAP>
+template <int BLOCK, int T, int TRIP, int SCAP, bool CPR, bool LAB>
 void launch_cull(const CullCfg &c, hipStream_t s, const float4 *pts,
                  const float4 *sph, const float *cpar, const float4 *shift,
                  double *part, float *lse, const TileArgs &a) {
-  hipLaunchKernelGGL((em_cull_kernel<BLOCK, T, TRIP, SCAP>), dim3(c.grid),
+  hipLaunchKernelGGL((em_cull_kernel<BLOCK, T, TRIP, SCAP, CPR, LAB>), dim3(c.grid),
                      dim3(BLOCK), c.lds, s, pts, sph, cpar, shift, part, lse, a);
 }
 
-template <int BLOCK, int T, int TRIP, int SCAP>
+template <int BLOCK, int T, int TRIP, int SCAP, bool CPR = false>
 bool make_cull_cfg(int K, int64_t n, CullCfg *out) {
   DevInfo di = dev_info();
   if (di.cus <= 0 || K > BLOCK) return false;  // one 64-component chunk per wave
-  const size_t lds = cull_lds_bytes<BLOCK, T, TRIP, SCAP>(K);
+  const size_t lds = cull_lds_bytes<BLOCK, T, TRIP, SCAP, CPR>(K);
   if (lds > (di.lds_max ? di.lds_max : 65536)) return false;
-  const void *fn = reinterpret_cast<const void *>(&em_cull_kernel<BLOCK, T, TRIP, SCAP>);
+  const void *fn =
+      reinterpret_cast<const void *>(&em_cull_kernel<BLOCK, T, TRIP, SCAP, CPR, false>);
+  const void *fl =
+      reinterpret_cast<const void *>(&em_cull_kernel<BLOCK, T, TRIP, SCAP, CPR, true>);
   if (lds > 65536 &&
-      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds) != hipSuccess)
+      (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+           hipSuccess ||
+       hipFuncSetAttribute(fl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+           hipSuccess))
     return false;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BLOCK, lds) !=
@@ -440,20 +447,29 @@ bool make_cull_cfg(int K, int64_t n, CullCfg *out) {
   out->trip = TRIP;
   out->grid = (int)std::min<int64_t>(ntiles, (int64_t)di.cus * per_cu);
   out->lds = lds;
-  out->launch = &launch_cull<BLOCK, T, TRIP, SCAP>;
+  out->launch = &launch_cull<BLOCK, T, TRIP, SCAP, CPR, false>;
+  out->launch_lab = &launch_cull<BLOCK, T, TRIP, SCAP, CPR, true>;
   return true;
 }
 
+// Shapes: block, tile, points per M-phase lane, E rows kept; "r": cull
+// parameters in registers and shifts from global memory (frees 64 B of LDS
+// per component).
 using MakeCull = bool (*)(int, int64_t, CullCfg *);
-constexpr int kNumCull = 8;
+constexpr int kNumCull = 14;
 const MakeCull kCull[kNumCull] = {
-    &make_cull_cfg<512, 128, 16, 64>, &make_cull_cfg<512, 256, 16, 32>,
-    &make_cull_cfg<512, 128, 16, 32>, &make_cull_cfg<1024, 128, 16, 64>,
-    &make_cull_cfg<512, 128, 8, 32>,  &make_cull_cfg<256, 128, 16, 32>,
-    &make_cull_cfg<256, 128, 8, 32>,  &make_cull_cfg<256, 64, 8, 32>};
-const char *const kCullName[kNumCull] = {"c512t128",    "c512t256",    "c512t128s32",
-                                         "c1024t128",   "c512t128p16", "c256t128",
-                                         "c256t128p16", "c256t64"};
+    &make_cull_cfg<512, 128, 16, 64>,        &make_cull_cfg<512, 256, 16, 32>,
+    &make_cull_cfg<512, 128, 16, 32>,        &make_cull_cfg<1024, 128, 16, 64>,
+    &make_cull_cfg<512, 128, 8, 32>,         &make_cull_cfg<256, 128, 16, 32>,
+    &make_cull_cfg<256, 128, 8, 32>,         &make_cull_cfg<256, 64, 8, 32>,
+    &make_cull_cfg<1024, 128, 16, 64, true>, &make_cull_cfg<1024, 128, 16, 32, true>,
+    &make_cull_cfg<512, 128, 8, 32, true>,   &make_cull_cfg<1024, 128, 16, 96, true>,
+    &make_cull_cfg<1024, 128, 16, 128, true>, &make_cull_cfg<1024, 64, 8, 128, true>};
+const char *const kCullName[kNumCull] = {
+    "c512t128",    "c512t256",   "c512t128s32",   "c1024t128",
+    "c512t128p16", "c256t128",   "c256t128p16",   "c256t64",
+    "c1024t128r",  "c1024t128s32r", "c512t128p16r", "c1024t128s96r",
+    "c1024t128s128r", "c1024t64r"};
 
 // Culling is on unless GMM_CULL=0 or GMM_TILE_SHAPE names a dense shape.
 bool pick_cull_cfg(int K, int64_t n, CullCfg *out) {
@@ -469,11 +485,14 @@ bool pick_cull_cfg(int K, int64_t n, CullCfg *out) {
       }
     return false;
   }
-  // measured on the depth frame: subsets of 8 points up to K = 128, of 16
-  // above; 1024-thread blocks beyond K = 512
-  const int order[2] = {K <= 128 ? 4 : K <= 512 ? 0 : 3, 3};
-  for (int i : order)
-    if (kCull[i](K, n, out)) {
+  // measured: subsets of 8 points up to K = 128, of 16 above (depth frame);
+  // beyond K = 512 1024-thread blocks with the cull parameters in registers
+  // and 128 E rows (LiDAR scan, K = 1000), fewer rows where LDS is short
+  static const int small[2] = {4, 3}, mid[2] = {0, 3}, large[4] = {12, 11, 8, 3};
+  const int *order = K <= 128 ? small : K <= 512 ? mid : large;
+  const int norder = K <= 512 ? 2 : 4;
+  for (int o = 0; o < norder; ++o)
+    if (const int i = order[o]; kCull[i](K, n, out)) {
       out->name = kCullName[i];
       return true;
     }
@@ -666,7 +685,7 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
                     float *lse, float *out_w = nullptr, float *out_mu = nullptr,
                     float *out_cov = nullptr) {
   const WsLayout &L = r.L;
-  const bool cull = r.cull && mode != kLabels;
+  const bool cull = r.cull;  // label passes too: a tile's components are its labels
   TileArgs a;
   a.ntiles = (int)(L.npad / (cull ? r.cc.tile : r.c.tile));
   a.K = r.K;
@@ -691,7 +710,8 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   }
   for (int rep = 0; rep < (timed ? g_prof.reps : 1); ++rep) {
     if (cull)
-      r.cc.launch(r.cc, r.s, at<float4>(r.ws, L.pts4), at<float4>(r.ws, L.tsph),
+      (mode == kLabels ? r.cc.launch_lab : r.cc.launch)(
+                  r.cc, r.s, at<float4>(r.ws, L.pts4), at<float4>(r.ws, L.tsph),
                   at<float>(r.ws, L.cpar[r.cur]), at<float4>(r.ws, L.shift[r.cur]),
                   at<double>(r.ws, L.part), lse, a);
     else

@@ -309,11 +309,14 @@ def test_graph_replay_matches_direct_launches():
 
 
 SHAPES = ["b512t64", "b1024t128", "b512t128", "b256t64", "b1024t64", "b1024t64c2"]
-CULL_SHAPES = ["c512t128", "c512t256", "c512t128s32", "c1024t128", "c512t128p16", "c256t128", "c256t128p16", "c256t64"]
+CULL_SHAPES = ["c512t128", "c512t256", "c512t128s32", "c1024t128", "c512t128p16",
+               "c256t128", "c256t128p16", "c256t64", "c1024t128r", "c1024t128s32r",
+               "c512t128p16r", "c1024t128s96r", "c1024t128s128r", "c1024t64r"]
 
 
 @pytest.mark.parametrize("shape", SHAPES + CULL_SHAPES)
-@pytest.mark.parametrize("K,n", [(100, 20011), (16, 5003), (200, 12000), (700, 9000)])
+@pytest.mark.parametrize("K,n", [(100, 20011), (16, 5003), (200, 12000), (700, 9000),
+                                 (1000, 12000)])
 def test_every_tile_shape_one_step_parity(shape, K, n, monkeypatch):
     """Each tile shape the autotuner may pick meets the one-step bar."""
     monkeypatch.setenv("GMM_TILE_SHAPE", shape)
@@ -386,6 +389,28 @@ def test_culled_matches_dense_and_oracle(K, n, order, monkeypatch):
     print(e_cull, e_dense)
     assert max(e_cull.values()) <= 1e-5, e_cull
     assert max(e_dense.values()) <= 1e-5, e_dense
+
+
+@pytest.mark.parametrize("shape", ["c512t128p16", "c512t128", "c1024t128s128r", "c1024t64r"])
+@pytest.mark.parametrize("K", [300, 1000])
+@pytest.mark.parametrize("sort", ["1", "0"])
+def test_culled_label_pass_with_scattered_labels(shape, K, sort, monkeypatch):
+    """Label passes run on the culled kernel with a tile's labels as its
+    component list.  Uniformly random labels put more distinct labels in a
+    tile than the kernel keeps E rows, so the one-hot rows are rebuilt in
+    several M rounds; with and without the spatial ordering."""
+    monkeypatch.setenv("GMM_TILE_SHAPE", shape)
+    monkeypatch.setenv("GMM_SORT", sort)
+    n = 20011
+    if _lib.tile_config(n, K) != shape:
+        pytest.skip("shape %s cannot run K=%d" % (shape, K))
+    _case("cull label pass %s K=%d sort=%s" % (shape, K, sort))
+    X = _depth_subset(n, seed=K + 1)
+    lab = np.random.default_rng(K).integers(0, K, n).astype(np.int32)
+    w, mu, cov, L = _fit(X, K, 0, labels=lab)
+    wr, mur, covr = oracle.mstep_labels(X, lab, K, 1e-3)
+    errs = {"pi": _rel(w, wr), "mu": _rel(mu, mur), "Sigma": _rel(cov, covr)}
+    assert max(errs.values()) <= 1e-5, errs
 
 
 def test_culled_far_points_take_the_dense_fallback():
