@@ -723,7 +723,7 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   const int nxt = 1 - r.cur;
   const int col0 = (mode == kSoftLogLik) ? kNStat * r.K : 0;
   const int ncx = (L.ncols - col0 + 63) / 64;
-  hipLaunchKernelGGL(reduce_rows_kernel, dim3(ncx, kRedChunks), dim3(256), 0,
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3(ncx, kRedChunksFit), dim3(256), 0,
                      r.s, at<double>(r.ws, L.part), rows, L.ncols, col0,
                      at<double>(r.ws, L.red));
   HIP_TRY(hipGetLastError());
