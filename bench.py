@@ -22,6 +22,9 @@ Prints one JSON line:
   batched         64 uneven depth frames (N_f ~ U[20k, 300k], K_f ~ U[16,
                   200]) fitted by one gmm_fit_batched call vs 64 sequential
                   gmm_fit calls (direct launches), same T
+  lidar           the large fit: a synthetic 64-ring LiDAR scan, N =
+                  2,000,000, K = 1000, T = 50, two-pass FP64 moments (and
+                  shifted one-pass moments for comparison), k-means++ labels
   cpu_baseline    the FP64 CPU oracle on a bounded sample of the same fit
 """
 from __future__ import annotations
@@ -49,9 +52,9 @@ PROFILE_REPS = 16           # tile launches per timed event pair
 # 256 MiB device copy (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all
 # of them).  Valid only for the kernel source and tile shape it was taken
 # on: any other reports null.
-TRAFFIC = {"kernel_src_sha256": "c0a237c304247eefe7215dcd36fd36010a6a299a865835f8da87ae651d6c35b8",
+TRAFFIC = {"kernel_src_sha256": "2bb2bf8a11aff4ffb3d28ad665aa4626c9d23ab17a65f8f6eea6234b94e20502",
            "tile_shape": "c512t128p16", "N": 307200, "K": 100,
-           "fetch_kib": 2655.07, "fetch_factor": 2.0,
+           "fetch_kib": 2658.08, "fetch_factor": 2.0,
            "write_kib": 6044.21, "write_factor": 1.0}
 
 
@@ -67,6 +70,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-iters", type=int, default=20)
+    ap.add_argument("--no-lidar", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device tensor copy "
                          "(a known-size reference for memory counters)")
@@ -151,6 +155,52 @@ def batched_vs_plain(T, reps=2):
                 "workload": "64 synthetic depth frames subsampled to "
                             "N_f~U[20000,300000], K_f~U[16,200], k-means++ "
                             "labels, lambda=1e-3"})
+    return out
+
+
+def lidar_fit(T=50, reps=3):
+    """The LiDAR-scan fit: N = 2,000,000, K = 1000, T iterations."""
+    import torch
+
+    import paper_2307_00071_amd as gmm
+    from paper_2307_00071_amd import _lib, synth
+
+    dev = torch.device("cuda:0")
+    K = 1000
+    X = synth.lidar_scan(0)
+    N = X.shape[0]
+    pts = torch.from_numpy(X).to(dev)
+    lab = torch.from_numpy(synth.kmeanspp_labels(X, K, 1)).to(dev)
+    ws = torch.empty(gmm.fit_workspace_bytes(N, K, T), dtype=torch.uint8, device=dev)
+    out = {"workload": "synthetic 64-ring LiDAR scan (elevation -25..+15 deg, "
+                       "0.2 deg azimuth, planes and cylinders up to 80 m, "
+                       "0.02 m range noise), k-means++ labels, lambda=1e-3",
+           "N": N, "K": K, "iters": T, "tile_shape": _lib.tile_config(N, K)}
+    for mode in ("two_pass", "shifted"):
+        def fit():
+            return gmm.fit(pts, K, iters=T, reg_covar=1e-3, labels=lab,
+                           moment_mode=mode, workspace=ws)
+        for _ in range(2):
+            fit()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fit()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[mode + "_ms"] = 1e3 * dt
+        out[mode + "_evals_per_s"] = N * K * T / dt
+        out[mode + "_final_loglik"] = float(r.loglik[-1].item())
+    _lib.profile_read()
+    _lib.profile_pairs()
+    _lib.profile_enable(1)
+    gmm.fit(pts, K, iters=T, reg_covar=1e-3, labels=lab, workspace=ws)
+    torch.cuda.synchronize()
+    _lib.profile_enable(0)
+    tile_ms, launches = _lib.profile_read()
+    pe, pa = _lib.profile_pairs()
+    out["tile_avg_launch_us"] = 1e3 * tile_ms / max(launches, 1)
+    out["evaluated_pair_fraction"] = pe / max(pa, 1)
     return out
 
 
@@ -251,6 +301,8 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_vs_plain(args.batched_iters)
+    if not args.no_lidar:
+        out["lidar"] = lidar_fit()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, lab, K, T, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -921,6 +921,9 @@ __device__ __forceinline__ uint64_t cull_ballot(const float4 *cp, float4 sp) {
 #ifndef GMM_CULL_WPE
 #define GMM_CULL_WPE 1
 #endif
+#ifndef GMM_CULL_EU
+#define GMM_CULL_EU 4  // E-phase components per step
+#endif
 
 // LDS of the culled tile loop (carved from the dynamic shared memory).
 struct CullLds {
@@ -1090,33 +1093,28 @@ __device__ __forceinline__ void cull_tiles(
       }
       __syncthreads();
     } else {
-    // ---- E-phase: slots rr, rr + R, ... of the active list, four at a time
+    // ---- E-phase: slots rr, rr + R, ... of the active list, EU at a time
     float s = 0.0f;
     {
+      constexpr int EU = GMM_CULL_EU;
       int sl = rr;
-      for (; sl + 3 * R < nact; sl += 4 * R) {
-        const int b0 = __builtin_amdgcn_readfirstlane(list[sl]);
-        const int b1 = __builtin_amdgcn_readfirstlane(list[sl + R]);
-        const int b2 = __builtin_amdgcn_readfirstlane(list[sl + 2 * R]);
-        const int b3 = __builtin_amdgcn_readfirstlane(list[sl + 3 * R]);
-        const float e0 = __builtin_amdgcn_exp2f(
-            comp_logterm(cpar + (size_t)b0 * kParStride, x.x, x.y, x.z));
-        const float e1 = __builtin_amdgcn_exp2f(
-            comp_logterm(cpar + (size_t)b1 * kParStride, x.x, x.y, x.z));
-        const float e2 = __builtin_amdgcn_exp2f(
-            comp_logterm(cpar + (size_t)b2 * kParStride, x.x, x.y, x.z));
-        const float e3 = __builtin_amdgcn_exp2f(
-            comp_logterm(cpar + (size_t)b3 * kParStride, x.x, x.y, x.z));
-        s += e0; s += e1; s += e2; s += e3;
-        if (sl + 3 * R < SCAP) {
-          E[sl * RS + tx] = e0;
-          E[(sl + R) * RS + tx] = e1;
-          E[(sl + 2 * R) * RS + tx] = e2;
-          E[(sl + 3 * R) * RS + tx] = e3;
+      for (; sl + (EU - 1) * R < nact; sl += EU * R) {
+        float e[EU];
+#pragma unroll
+        for (int u = 0; u < EU; ++u) {
+          const int b = __builtin_amdgcn_readfirstlane(list[sl + u * R]);
+          e[u] = __builtin_amdgcn_exp2f(
+              comp_logterm(cpar + (size_t)b * kParStride, x.x, x.y, x.z));
+        }
+#pragma unroll
+        for (int u = 0; u < EU; ++u) s += e[u];
+        if (sl + (EU - 1) * R < SCAP) {
+#pragma unroll
+          for (int u = 0; u < EU; ++u) E[(sl + u * R) * RS + tx] = e[u];
         } else {
-          if (sl < SCAP) E[sl * RS + tx] = e0;
-          if (sl + R < SCAP) E[(sl + R) * RS + tx] = e1;
-          if (sl + 2 * R < SCAP) E[(sl + 2 * R) * RS + tx] = e2;
+#pragma unroll
+          for (int u = 0; u < EU - 1; ++u)
+            if (sl + u * R < SCAP) E[(sl + u * R) * RS + tx] = e[u];
         }
       }
       for (; sl < nact; sl += R) {
@@ -1320,35 +1318,38 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
 // Two fence-free launches after each tile pass:
 //  reduce_rows_kernel  red2[y][c] = sum of part[r][c] over the y-th of
 //                      gridDim.y chunks of rows; a block owns 64 columns x
-//                      one chunk, its 4 waves take interleaved rows and are
-//                      added in wave order (up to 16 loads in flight, adds
-//                      in row order).
+//                      one chunk, its NT/64 waves take interleaved rows and
+//                      are added in wave order (up to 16 loads in flight,
+//                      adds in row order).
 //  update_kernel       one block: tot[c] = sum_y red2[y][c] in y order, then
 //                      the M-step (em_update_block) from LDS.
-// Fits use kRedChunksFit chunks: the single update block then has all of a
-// thread's loads (4 columns x 4 rows) in flight at once, which measured
-// faster than more, shorter chunks (K = 100: 16 chunks cost 0.28 ms more per
-// 100-iteration fit).  The backward pass reduces into kRedChunks chunks.
+// Fits use kRedChunksFit chunks and 1024-thread reduce blocks: the single
+// update block then has all of a thread's loads (4 columns x 4 rows) in
+// flight at once.  Measured per 100-iteration fit at K = 100: 16 chunks
+// 0.28 ms slower, 2 or 1 chunk 0.14 / 0.43 ms slower, 256-thread reduce
+// blocks 0.07 ms slower.  The backward pass reduces into kRedChunks chunks.
 constexpr int kRedChunks = 16;
 constexpr int kRedChunksFit = 4;
 constexpr int kUpdThreads = 1024;
 
-__global__ __launch_bounds__(256) void reduce_rows_kernel(
+template <int NT>
+__global__ __launch_bounds__(NT) void reduce_rows_kernel(
     const double *__restrict__ part, int nrows, int ncols, int col0,
     double *__restrict__ red2) {
-  __shared__ double sh[4][64];
+  constexpr int NW = NT / 64;
+  __shared__ double sh[NW][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = col0 + blockIdx.x * 64 + lane;
   const int cs = (nrows + (int)gridDim.y - 1) / (int)gridDim.y;
   const int r0 = blockIdx.y * cs, r1 = min(nrows, r0 + cs);
   double s = 0.0;
   if (c < ncols) {
-    // the wave's rows r0 + wv + 4 i: up to 16 loads in flight, added in order
-    for (int base = r0 + wv; base < r1; base += 64) {
+    // the wave's rows r0 + wv + NW i: up to 16 loads in flight, added in order
+    for (int base = r0 + wv; base < r1; base += 16 * NW) {
       double v[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        const int r = base + 4 * i;
+        const int r = base + NW * i;
         v[i] = r < r1 ? part[(size_t)r * ncols + c] : 0.0;
       }
 #pragma unroll
@@ -1357,9 +1358,12 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(
   }
   sh[wv][lane] = s;
   __syncthreads();
-  if (wv == 0 && c < ncols)
-    red2[(size_t)blockIdx.y * ncols + c] =
-        ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+  if (wv == 0 && c < ncols) {
+    double t = sh[0][lane];
+#pragma unroll
+    for (int j = 1; j < NW; ++j) t += sh[j][lane];
+    red2[(size_t)blockIdx.y * ncols + c] = t;
+  }
 }
 
 struct UpdArgs {

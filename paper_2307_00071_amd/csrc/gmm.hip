@@ -723,7 +723,7 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   const int nxt = 1 - r.cur;
   const int col0 = (mode == kSoftLogLik) ? kNStat * r.K : 0;
   const int ncx = (L.ncols - col0 + 63) / 64;
-  hipLaunchKernelGGL(reduce_rows_kernel, dim3(ncx, kRedChunksFit), dim3(256), 0,
+  hipLaunchKernelGGL(reduce_rows_kernel<1024>, dim3(ncx, kRedChunksFit), dim3(1024), 0,
                      r.s, at<double>(r.ws, L.part), rows, L.ncols, col0,
                      at<double>(r.ws, L.red));
   HIP_TRY(hipGetLastError());
@@ -1748,7 +1748,7 @@ gmm_status gmm_loglik_backward(const float *pts, int64_t n, const float *pose6,
             at<double>(ws, r.L.part), g_pts, a, n);
   HIP_TRY(hipGetLastError());
   const int ncx = (r.L.ncols + 63) / 64;
-  hipLaunchKernelGGL(reduce_rows_kernel, dim3(ncx, kRedChunks), dim3(256), 0,
+  hipLaunchKernelGGL(reduce_rows_kernel<256>, dim3(ncx, kRedChunks), dim3(256), 0,
                      r.s, at<double>(ws, r.L.part), bc.grid, r.L.ncols, 0,
                      at<double>(ws, r.L.red));
   HIP_TRY(hipGetLastError());
