@@ -10,7 +10,9 @@ Functions follow the paper's Sec. V "Expectation Maximization":
 eq. 1 (responsibilities), eq. 2 (log-domain E-step), eq. 3 (Cholesky
 precision form of the Gaussian log-density); the M-step is the standard
 full-covariance maximum-likelihood update (the paper names it without
-formulas).
+formulas).  ``kmeanspp`` is the k-means++ seeding read into the randomised
+k-means initialisation that precedes EM in the same section (its draws are
+inputs; its running sums follow a fixed chunked order).
 """
 from __future__ import annotations
 
@@ -66,9 +68,12 @@ def _load():
         lib.oracle_loglik_pose.argtypes = [i64, D, D, i32, D, D, D, D, D]
         lib.oracle_loglik_grad.argtypes = [i64, D, D, i32, D, D, D, dbl,
                                            D, D, D, D, D]
+        lib.oracle_kmeanspp.argtypes = [i64, D, i32, D,
+                                        ctypes.POINTER(ctypes.c_int64), I32]
         for name in ("oracle_component_terms", "oracle_estep",
                      "oracle_mstep_labels", "oracle_em_step", "oracle_fit",
-                     "oracle_loglik_pose", "oracle_loglik_grad"):
+                     "oracle_loglik_pose", "oracle_loglik_grad",
+                     "oracle_kmeanspp"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -207,3 +212,23 @@ def loglik_grad(X, pose6, w, mu, cov, grad_L=1.0):
         _d(out["pose"]), _d(out["pts"]), _d(out["w"]), _d(out["mu"]),
         _d(out["cov"])))
     return out
+
+
+def kmeanspp(X, K, u):
+    """k-means++ D^2 seeding with the K uniform draws u (in [0, 1)) given,
+    and nearest-seed labels (ties to the lowest index).  Returns
+    (centre indices int64 (K,), labels int32 (N,)).  The running sums that
+    turn a draw into an index follow a fixed order (chunks of 256 points,
+    groups of 64 chunks); see oracle_kmeanspp in gmm_oracle.c."""
+    X = _f64(X).reshape(-1, 3)
+    u = _f64(u)
+    K = int(K)
+    if u.shape != (K,):
+        raise OracleError("need K uniform draws")
+    N = X.shape[0]
+    cen = np.zeros(K, dtype=np.int64)
+    lab = np.zeros(N, dtype=np.int32)
+    _check(_load().oracle_kmeanspp(
+        N, _d(X), K, _d(u), cen.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        lab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return cen, lab

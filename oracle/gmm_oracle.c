@@ -556,3 +556,136 @@ int oracle_loglik_grad(int64_t N, const double *X, const double *pose6, int K,
     free(tot); free(acc); free(P); free(c); free(Si);
     return OR_OK;
 }
+
+/* ---- k-means++ seeding (the initialisation that precedes EM) --------------
+ *
+ * The paper starts EM from a responsibility matrix given by a randomised
+ * k-means step (Sec. V, before "Expectation Maximization"; KInit).  The
+ * reading used here is plain k-means++ D^2 seeding (Arthur & Vassilvitskii,
+ * 2007) with one trial per centre and hard nearest-seed labels, no Lloyd
+ * iterations.  The K random draws are inputs: u[j] in [0, 1).
+ *
+ *   centre 0: index floor(u[0] * N) (at most N - 1);
+ *   D2_i = squared distance from x_i to the nearest centre chosen so far;
+ *   centre j >= 1: with W = sum_i D2_i and t = u[j] * W, the first index
+ *     whose running sum of D2 exceeds t (so index i is drawn with
+ *     probability D2_i / W); if W = 0 every point is a centre already and
+ *     centre j repeats centre j - 1;
+ *   label_i = index j of the nearest centre (the lowest j on ties).
+ *
+ * Because a floating-point running sum depends on its order, the order is
+ * fixed: D2 is summed sequentially within chunks of KPP_CHUNK points, the
+ * chunk totals sequentially within groups of KPP_GROUP chunks, and the
+ * group totals sequentially; the search walks groups, then the chunks of
+ * the chosen group, then the points of the chosen chunk, each time
+ * comparing the running sum with what is left of t.  Squared distances are
+ * ((dx^2 + dy^2) + dz^2) in double with every operation rounded on its own
+ * (the file is compiled without contraction). */
+#define KPP_CHUNK 256
+#define KPP_GROUP 64
+
+static double kpp_d2(const double *a, const double *b) {
+  const double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
+  return (d0 * d0 + d1 * d1) + d2 * d2;
+}
+
+/* First i in [0, m) whose running sum v[0] + ... + v[i] exceeds t; when
+ * none does (rounding at the end of the range), the last i with v[i] > 0.
+ * *before receives the running sum before i.  Returns -1 if every v is 0. */
+static int64_t kpp_search(const double *v, int64_t m, double t, double *before) {
+  double acc = 0.0;
+  for (int64_t i = 0; i < m; ++i) {
+    const double nx = acc + v[i];
+    if (nx > t) {
+      *before = acc;
+      return i;
+    }
+    acc = nx;
+  }
+  int64_t last = -1;
+  for (int64_t i = m - 1; i >= 0; --i)
+    if (v[i] > 0.0) {
+      last = i;
+      break;
+    }
+  acc = 0.0;
+  for (int64_t i = 0; i < last; ++i) acc += v[i];
+  *before = acc;
+  return last;
+}
+
+int oracle_kmeanspp(int64_t N, const double *X, int K, const double *u,
+                    int64_t *centres, int32_t *labels) {
+  if (N <= 0 || K <= 0 || K > N || !X || !u || !centres) return OR_ERR_ARG;
+  for (int j = 0; j < K; ++j)
+    if (!(u[j] >= 0.0 && u[j] < 1.0)) return OR_ERR_ARG;
+  for (int64_t i = 0; i < 3 * N; ++i)
+    if (!isfinite(X[i])) return OR_ERR_NONFINITE;
+  const int64_t nch = (N + KPP_CHUNK - 1) / KPP_CHUNK;
+  const int64_t ngr = (nch + KPP_GROUP - 1) / KPP_GROUP;
+  double *D = malloc((size_t)N * sizeof(double));
+  double *T = malloc((size_t)nch * sizeof(double));
+  double *U = malloc((size_t)ngr * sizeof(double));
+  if (!D || !T || !U) {
+    free(D); free(T); free(U);
+    return OR_ERR_OOM;
+  }
+  int64_t c0 = (int64_t)(u[0] * (double)N);
+  if (c0 > N - 1) c0 = N - 1;
+  centres[0] = c0;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; ++i) D[i] = kpp_d2(X + 3 * i, X + 3 * c0);
+  for (int j = 1; j < K; ++j) {
+    for (int64_t c = 0; c < nch; ++c) {
+      const int64_t lo = c * KPP_CHUNK, hi = lo + KPP_CHUNK < N ? lo + KPP_CHUNK : N;
+      double s = 0.0;
+      for (int64_t i = lo; i < hi; ++i) s += D[i];
+      T[c] = s;
+    }
+    for (int64_t g = 0; g < ngr; ++g) {
+      const int64_t lo = g * KPP_GROUP, hi = lo + KPP_GROUP < nch ? lo + KPP_GROUP : nch;
+      double s = 0.0;
+      for (int64_t c = lo; c < hi; ++c) s += T[c];
+      U[g] = s;
+    }
+    double W = 0.0;
+    for (int64_t g = 0; g < ngr; ++g) W += U[g];
+    int64_t pick = centres[j - 1];
+    if (W > 0.0) {
+      const double t = u[j] * W;
+      double b;
+      const int64_t g = kpp_search(U, ngr, t, &b);
+      const double t1 = t - b;
+      const int64_t clo = g * KPP_GROUP;
+      const int64_t cm = clo + KPP_GROUP < nch ? KPP_GROUP : nch - clo;
+      const int64_t c = clo + kpp_search(T + clo, cm, t1, &b);
+      const double t2 = t1 - b;
+      const int64_t ilo = c * KPP_CHUNK;
+      const int64_t im = ilo + KPP_CHUNK < N ? KPP_CHUNK : N - ilo;
+      pick = ilo + kpp_search(D + ilo, im, t2, &b);
+    }
+    centres[j] = pick;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+      const double d = kpp_d2(X + 3 * i, X + 3 * pick);
+      if (d < D[i]) D[i] = d;
+    }
+  }
+  if (labels) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+      double best = kpp_d2(X + 3 * i, X + 3 * centres[0]);
+      int32_t l = 0;
+      for (int j = 1; j < K; ++j) {
+        const double d = kpp_d2(X + 3 * i, X + 3 * centres[j]);
+        if (d < best) {
+          best = d;
+          l = j;
+        }
+      }
+      labels[i] = l;
+    }
+  }
+  free(D); free(T); free(U);
+  return OR_OK;
+}
