@@ -181,6 +181,36 @@ gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
                            const gmm_fit_opts *opts, void *ws, size_t ws_bytes,
                            void *stream);
 
+/* ------------------------------------------------------------ k-means++
+ * Seeding of a fit: the paper starts EM from a randomised k-means step
+ * (Sec. V); this is k-means++ D^2 seeding (Arthur & Vassilvitskii, 2007),
+ * one trial per centre, with hard nearest-centre labels and no Lloyd
+ * iterations.  The K random draws are the caller's: u[j] in [0, 1).
+ *   centre 0 = floor(u[0] n) (at most n - 1);
+ *   centre j = the first point whose running sum of D2 exceeds u[j] W,
+ *     D2_i = squared distance from x_i to the nearest earlier centre and
+ *     W = sum_i D2_i, so point i is drawn with probability D2_i / W; when
+ *     W = 0 (every point on a centre) centre j repeats centre j - 1;
+ *   labels[i] = the nearest centre, the lowest j on ties.
+ * Distances are ((dx^2 + dy^2) + dz^2) in double, each operation rounded
+ * on its own.  The running sums have a fixed order - sequential within
+ * chunks of 256 points, chunk totals sequential within groups of 64
+ * chunks, group totals sequential; the search walks groups, then chunks,
+ * then points - so the centres are reproducible and equal those of any
+ * implementation that follows the same order.
+ *
+ * pts: device, n x 3 float32.  u: device, k doubles.  centres: device, k
+ * int64 indices into pts (output).  labels: device, n int32 in [0, k)
+ * (output; NULL skips the labels).  1 <= k <= min(n, GMM_MAX_K).
+ * Synchronises with `stream` once at the end.  Errors: INVALID_ARG (sizes,
+ * NULL pointers, a draw outside [0, 1)), NONFINITE (a non-finite point),
+ * OOM / DEVICE as for the other entry points; the outputs are unspecified
+ * after an error. */
+size_t gmm_kmeanspp_workspace_size(int64_t n, int32_t k);
+gmm_status gmm_kmeanspp(const float *pts, int64_t n, int32_t k, const double *u,
+                        int64_t *centres, int32_t *labels, void *ws, size_t ws_bytes,
+                        void *stream);
+
 /* ------------------------------------------------------------ autotuning
  * With autotuning on (gmm_set_autotune(1), or GMM_AUTOTUNE=1 in the
  * environment), the first gmm_fit for a new (device arch, K, N bucket =

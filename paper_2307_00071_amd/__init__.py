@@ -14,7 +14,7 @@ import ctypes
 from . import _lib
 
 __all__ = ["fit", "fit_batched", "loglik", "loglik_backward", "GMMLogLik",
-           "FitResult"]
+           "FitResult", "kmeanspp"]
 
 
 def _torch():
@@ -280,3 +280,38 @@ class _LazyAutograd:
 
 
 GMMLogLik = _LazyAutograd()
+
+
+def kmeanspp_workspace_bytes(n, k):
+    return int(_lib.load().gmm_kmeanspp_workspace_size(int(n), int(k)))
+
+
+def kmeanspp(points, k, seed=0, u=None, workspace=None):
+    """k-means++ seeding on the GPU (gmm_kmeanspp): K centres by D^2
+    sampling and the nearest-centre label of every point, the start of a
+    fit (``fit(points, k, labels=labels)``).
+
+    ``u`` holds the K draws in [0, 1) (float64, any device); by default
+    they come from ``numpy.random.default_rng(seed).random(k)``.  Returns
+    (labels int32 (N,), centre indices int64 (K,)), on the points' device."""
+    import numpy as np
+    torch = _torch()
+    lib = _lib.load()
+    pts = _check_points(points)
+    dev = pts.device
+    n, k = pts.shape[0], int(k)
+    if u is None:
+        u = np.random.default_rng(seed).random(k)
+    ut = torch.as_tensor(u, dtype=torch.float64).to(dev).contiguous()
+    if ut.shape != (k,):
+        raise ValueError("u must hold k draws")
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    centres = torch.empty(k, dtype=torch.int64, device=dev)
+    if workspace is None:
+        nb = kmeanspp_workspace_bytes(n, k)
+        workspace = _workspace(nb, dev) if nb else None
+    _lib.check(lib.gmm_kmeanspp(_ptr(pts), n, k, _ptr(ut), _ptr(centres), _ptr(labels),
+                                _ptr(workspace),
+                                0 if workspace is None else workspace.numel(),
+                                _stream(dev)))
+    return labels, centres

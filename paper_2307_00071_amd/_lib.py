@@ -26,6 +26,7 @@ EXPORTS = (
     "gmm_fit_batched_workspace_size", "gmm_fit_batched",
     "gmm_set_autotune", "gmm_tile_config",
     "gmm_profile_enable", "gmm_profile_read", "gmm_profile_pairs",
+    "gmm_kmeanspp_workspace_size", "gmm_kmeanspp",
 )
 
 
@@ -94,6 +95,10 @@ def load():
     lib.gmm_profile_pairs.argtypes = [ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_int64)]
     lib.gmm_profile_pairs.restype = ctypes.c_int
+    lib.gmm_kmeanspp_workspace_size.argtypes = [i64, i32]
+    lib.gmm_kmeanspp_workspace_size.restype = sz
+    lib.gmm_kmeanspp.argtypes = [vp, i64, i32, vp, vp, vp, vp, sz, vp]
+    lib.gmm_kmeanspp.restype = ctypes.c_int
     _lib = lib
     return lib
 

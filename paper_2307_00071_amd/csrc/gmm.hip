@@ -18,6 +18,7 @@
 
 #include "em_device.hpp"
 #include "order_device.hpp"
+#include "kinit_device.hpp"
 #include "gmm.h"
 
 namespace {
@@ -1627,6 +1628,74 @@ gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
   uint32_t bits = 0;
   HIP_TRY(hipMemcpyAsync(&bits, at<uint32_t>(ws, bp.status), sizeof bits,
                          hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return status_from_bits(bits);
+}
+
+// ------------------------------------------------------- k-means++ seeding
+
+struct KppLayout {
+  size_t status, D, T, U, total;
+  int64_t nch, ngr;
+};
+
+KppLayout kpp_layout(int64_t n) {
+  KppLayout L;
+  L.nch = (n + kKppChunk - 1) / kKppChunk;
+  L.ngr = (L.nch + kKppGroup - 1) / kKppGroup;
+  size_t o = 0;
+  L.status = o; o = align256(o + sizeof(uint32_t));
+  L.D = o; o = align256(o + (size_t)n * sizeof(double));
+  L.T = o; o = align256(o + (size_t)L.nch * sizeof(double));
+  L.U = o; o = align256(o + (size_t)L.ngr * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+size_t gmm_kmeanspp_workspace_size(int64_t n, int32_t k) {
+  g_err[0] = 0;
+  if (check_sizes(n, k, true) != GMM_OK) return 0;
+  return kpp_layout(n).total;
+}
+
+gmm_status gmm_kmeanspp(const float *pts, int64_t n, int32_t k, const double *u,
+                        int64_t *centres, int32_t *labels, void *ws, size_t ws_bytes,
+                        void *stream) {
+  g_err[0] = 0;
+  gmm_status st = check_sizes(n, k, true);
+  if (st != GMM_OK) return st;
+  if (!pts || !u || !centres) return fail(GMM_ERR_INVALID_ARG, "NULL pointer argument");
+  const KppLayout L = kpp_layout(n);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  WsGuard guard;
+  if ((st = get_ws(&ws, &ws_bytes, L.total, s, &guard)) != GMM_OK) return st;
+  uint32_t *status = at<uint32_t>(ws, L.status);
+  double *D = at<double>(ws, L.D), *T = at<double>(ws, L.T), *U = at<double>(ws, L.U);
+  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, s, status, nullptr, 0,
+                     nullptr, 0);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(kpp_first_kernel, dim3(1), dim3(256), 0, s, u, k, n, centres,
+                     status);
+  HIP_TRY(hipGetLastError());
+  for (int j = 1; j < k; ++j) {
+    hipLaunchKernelGGL(kpp_update_kernel,
+                       dim3((unsigned)((L.nch + kKppUpdChunks - 1) / kKppUpdChunks)),
+                       dim3(kKppUpdThreads), 0, s, pts, n, centres, j - 1, D, T, L.nch,
+                       status);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(kpp_select_kernel, dim3(1), dim3(kKppSelThreads), 0, s, D, T, U,
+                       n, u, j, centres);
+    HIP_TRY(hipGetLastError());
+  }
+  if (labels) {
+    hipLaunchKernelGGL(kpp_label_kernel,
+                       dim3((unsigned)((n + kKppLabelThreads - 1) / kKppLabelThreads)),
+                       dim3(kKppLabelThreads), (size_t)k * 3 * sizeof(double), s, pts, n,
+                       centres, k, labels, status);
+    HIP_TRY(hipGetLastError());
+  }
+  uint32_t bits = 0;
+  HIP_TRY(hipMemcpyAsync(&bits, status, sizeof bits, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return status_from_bits(bits);
 }

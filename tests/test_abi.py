@@ -64,3 +64,16 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_kmeanspp_host_checks(lib):
+    """Sizes and NULL pointers are rejected on the host, before any
+    device work is enqueued."""
+    assert lib.gmm_kmeanspp_workspace_size(0, 1) == 0
+    assert lib.gmm_kmeanspp_workspace_size(10, 11) == 0
+    assert lib.gmm_kmeanspp_workspace_size(10, 0) == 0
+    assert lib.gmm_kmeanspp_workspace_size(1000, 10) > 8000
+    st = lib.gmm_kmeanspp(None, 100, 4, None, None, None, None, 0, None)
+    assert st == 1
+    st = lib.gmm_kmeanspp(None, 3, 4, None, None, None, None, 0, None)
+    assert st == 1

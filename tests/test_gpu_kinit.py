@@ -1,0 +1,132 @@
+"""GPU k-means++ seeding (gmm_kmeanspp through the C ABI) against the
+oracle's: the same draws must give exactly the same centre indices and
+labels (both follow one fixed running-sum order and round every distance
+operation on its own, so the comparison is bit-exact)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2307_00071_amd as gmm
+from paper_2307_00071_amd import _lib, synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _case(name):
+    print("case:", name, flush=True)
+
+
+def _both(X, K, u):
+    Xf = np.ascontiguousarray(X, dtype=np.float32)
+    lab, cen = gmm.kmeanspp(torch.from_numpy(Xf).to(DEV), K, u=u)
+    torch.cuda.synchronize()
+    rc, rl = oracle.kmeanspp(Xf.astype(np.float64), K, u)
+    return cen.cpu().numpy(), lab.cpu().numpy(), rc, rl
+
+
+def _depth_subset(n, seed):
+    X = synth.depth_frame(seed)
+    rng = np.random.default_rng(seed + 5)
+    return np.ascontiguousarray(X[np.sort(rng.choice(X.shape[0], n, replace=False))])
+
+
+CASES = [
+    ("blobs", 10000, 8), ("int-cloud", 20000, 12), ("depth-ragged", 16385, 37),
+    ("depth-ragged", 257, 257), ("depth-ragged", 300, 1), ("one-point", 1, 1),
+    ("depth-ragged", 70001, 150),
+]
+
+
+@pytest.mark.parametrize("kind,n,K", CASES)
+def test_kmeanspp_matches_oracle(kind, n, K):
+    _case("kmeanspp %s n=%d K=%d" % (kind, n, K))
+    if kind == "blobs":
+        X = synth.gaussian_blobs(0, n_per=n // 8)[0]
+    elif kind == "int-cloud":
+        X = np.random.default_rng(3).integers(0, 40, (n, 3)).astype(np.float32)
+    elif kind == "one-point":
+        X = np.array([[0.5, -1.0, 2.0]], dtype=np.float32)
+    else:
+        X = _depth_subset(n, seed=K)
+    u = np.random.default_rng(n + K).random(K)
+    cen, lab, rc, rl = _both(X, K, u)
+    np.testing.assert_array_equal(cen, rc)
+    np.testing.assert_array_equal(lab, rl)
+
+
+def test_kmeanspp_depth_frame_full():
+    _case("kmeanspp depth frame N=307200 K=100")
+    X = synth.depth_frame(0)
+    u = np.random.default_rng(1).random(100)
+    cen, lab, rc, rl = _both(X, 100, u)
+    np.testing.assert_array_equal(cen, rc)
+    np.testing.assert_array_equal(lab, rl)
+
+
+def test_kmeanspp_lidar_scan_full():
+    _case("kmeanspp lidar N=2000000 K=1000")
+    X = synth.lidar_scan(0)
+    u = np.random.default_rng(1).random(1000)
+    cen, lab, rc, rl = _both(X, 1000, u)
+    np.testing.assert_array_equal(cen, rc)
+    np.testing.assert_array_equal(lab, rl)
+
+
+def test_kmeanspp_more_groups_than_one_stage():
+    """n > 1024 groups of 64 x 256 points: the group totals are walked in
+    stages (the staged search path)."""
+    _case("kmeanspp n=17000000 K=4")
+    X = np.random.default_rng(8).uniform(-50, 50, (17_000_000, 3)).astype(np.float32)
+    u = np.array([0.3, 0.999, 0.5, 0.01])
+    cen, lab, rc, rl = _both(X, 4, u)
+    np.testing.assert_array_equal(cen, rc)
+    np.testing.assert_array_equal(lab, rl)
+
+
+def test_kmeanspp_degenerate_inputs():
+    _case("kmeanspp degenerate")
+    X = np.tile(np.array([[1.5, -2.0, 3.25]], dtype=np.float32), (600, 1))
+    cen, lab, rc, rl = _both(X, 5, np.array([0.3, 0.1, 0.9, 0.5, 0.0]))
+    np.testing.assert_array_equal(cen, rc)
+    assert (cen == cen[0]).all() and not lab.any()
+    X = _depth_subset(5000, 9)
+    X[:2000] = X[0]
+    u = np.array([0.0, 0.0, 1.0 - 2.0 ** -53, 0.5, 1.0 - 2.0 ** -53, 0.25])
+    cen, lab, rc, rl = _both(X, 6, u)
+    np.testing.assert_array_equal(cen, rc)
+    np.testing.assert_array_equal(lab, rl)
+
+
+def test_kmeanspp_reports_bad_draws_and_points():
+    _case("kmeanspp errors")
+    X = torch.from_numpy(_depth_subset(1000, 2)).to(DEV)
+    with pytest.raises(_lib.GmmError) as e:
+        gmm.kmeanspp(X, 4, u=np.array([0.1, 0.2, 1.0, 0.3]))
+    assert e.value.status == 1
+    Xn = X.clone()
+    Xn[17, 2] = float("nan")
+    with pytest.raises(_lib.GmmError) as e:
+        gmm.kmeanspp(Xn, 4, seed=0)
+    assert e.value.status == 3
+    with pytest.raises(_lib.GmmError) as e:
+        gmm.kmeanspp(X[:3], 4, seed=0)
+    assert e.value.status == 1
+
+
+def test_kmeanspp_then_fit_matches_oracle():
+    """GPU seeding feeds the GPU fit; the oracle fits from its own seeding
+    of the same draws (identical labels), final L within the fit bar."""
+    _case("kmeanspp then fit")
+    X = _depth_subset(30000, 4)
+    K, T = 40, 20
+    Xt = torch.from_numpy(X).to(DEV)
+    lab, _ = gmm.kmeanspp(Xt, K, seed=7)
+    r = gmm.fit(Xt, K, iters=T, reg_covar=1e-3, labels=lab)
+    torch.cuda.synchronize()
+    _, rl = oracle.kmeanspp(X.astype(np.float64), K, np.random.default_rng(7).random(K))
+    np.testing.assert_array_equal(lab.cpu().numpy(), rl)
+    Lo = oracle.fit(X, K, 1e-3, T, labels=rl)[3]
+    Lg = r.loglik.cpu().numpy()
+    assert abs(Lg[-1] - Lo[-1]) <= 1e-4 * max(abs(Lo[-1]), X.shape[0])
