@@ -24,7 +24,11 @@ Prints one JSON line:
                   gmm_fit calls (direct launches), same T
   lidar           the large fit: a synthetic 64-ring LiDAR scan, N =
                   2,000,000, K = 1000, T = 50, two-pass FP64 moments (and
-                  shifted one-pass moments for comparison), k-means++ labels
+                  shifted one-pass moments for comparison), started from the
+                  GPU k-means++ seeding
+  kinit           k-means++ seeding on the GPU (gmm_kmeanspp) at the depth
+                  frame (K = 100) and the LiDAR scan (K = 1000), beside the
+                  oracle's seeding of the same draws on the host cores
   cpu_baseline    the FP64 CPU oracle on a bounded sample of the same fit
 """
 from __future__ import annotations
@@ -54,7 +58,7 @@ PROFILE_REPS = 16           # tile launches per timed event pair
 # on: any other reports null.
 TRAFFIC = {"kernel_src_sha256": "2bb2bf8a11aff4ffb3d28ad665aa4626c9d23ab17a65f8f6eea6234b94e20502",
            "tile_shape": "c512t128p16", "N": 307200, "K": 100,
-           "fetch_kib": 2658.08, "fetch_factor": 2.0,
+           "fetch_kib": 2660.08, "fetch_factor": 2.0,
            "write_kib": 6044.21, "write_factor": 1.0}
 
 
@@ -71,6 +75,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-iters", type=int, default=20)
     ap.add_argument("--no-lidar", action="store_true")
+    ap.add_argument("--no-kinit", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device tensor copy "
                          "(a known-size reference for memory counters)")
@@ -170,11 +175,12 @@ def lidar_fit(T=50, reps=3):
     X = synth.lidar_scan(0)
     N = X.shape[0]
     pts = torch.from_numpy(X).to(dev)
-    lab = torch.from_numpy(synth.kmeanspp_labels(X, K, 1)).to(dev)
+    lab, _ = gmm.kmeanspp(pts, K, seed=1)
     ws = torch.empty(gmm.fit_workspace_bytes(N, K, T), dtype=torch.uint8, device=dev)
     out = {"workload": "synthetic 64-ring LiDAR scan (elevation -25..+15 deg, "
                        "0.2 deg azimuth, planes and cylinders up to 80 m, "
-                       "0.02 m range noise), k-means++ labels, lambda=1e-3",
+                       "0.02 m range noise), GPU k-means++ labels (draws from "
+                       "seed 1), lambda=1e-3",
            "N": N, "K": K, "iters": T, "tile_shape": _lib.tile_config(N, K)}
     for mode in ("two_pass", "shifted"):
         def fit():
@@ -201,6 +207,44 @@ def lidar_fit(T=50, reps=3):
     pe, pa = _lib.profile_pairs()
     out["tile_avg_launch_us"] = 1e3 * tile_ms / max(launches, 1)
     out["evaluated_pair_fraction"] = pe / max(pa, 1)
+    return out
+
+
+def kinit_bench(reps=3, cpu=True):
+    """GPU k-means++ seeding against the oracle's (same draws)."""
+    import numpy as np
+    import torch
+
+    import paper_2307_00071_amd as gmm
+    from paper_2307_00071_amd import synth
+
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, X, K in (("depth_frame", synth.depth_frame(0), 100),
+                       ("lidar_scan", synth.lidar_scan(0), 1000)):
+        N = X.shape[0]
+        pts = torch.from_numpy(X).to(dev)
+        u = np.random.default_rng(1).random(K)
+        ws = torch.empty(gmm.kmeanspp_workspace_bytes(N, K), dtype=torch.uint8, device=dev)
+        gmm.kmeanspp(pts, K, u=u, workspace=ws)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            lab, cen = gmm.kmeanspp(pts, K, u=u, workspace=ws)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        r = {"N": N, "K": K, "gpu_ms": 1e3 * best}
+        if cpu:
+            import oracle
+            t0 = time.perf_counter()
+            rc, rl = oracle.kmeanspp(X.astype(np.float64), K, u)
+            r["cpu_baseline"] = {"ms": 1e3 * (time.perf_counter() - t0),
+                                 "cores": oracle.get_threads(), "kind": "oracle",
+                                 "sample": "the whole seeding, same draws"}
+            r["identical_to_oracle"] = bool((cen.cpu().numpy() == rc).all() and
+                                            (lab.cpu().numpy() == rl).all())
+        out[name] = r
     return out
 
 
@@ -303,6 +347,8 @@ def main():
         out["batched"] = batched_vs_plain(args.batched_iters)
     if not args.no_lidar:
         out["lidar"] = lidar_fit()
+    if not args.no_kinit:
+        out["kinit"] = kinit_bench(cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, lab, K, T, args.cpu_seconds)
     print(json.dumps(out), flush=True)
