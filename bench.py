@@ -251,9 +251,9 @@ def kinit_bench(reps=3, cpu=True):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; the fit of one "
-              "frame runs on a single MI355X (multi-GPU sharding is a design "
-              "note, not built)", file=sys.stderr)
+        print("bench.py: measures one GPU only; the fit of one frame runs "
+              "on a single MI355X (sharding over several GPUs is not "
+              "implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
