@@ -863,11 +863,11 @@ __device__ __forceinline__ float dpp_add_mirror(float v) {
   return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, true));
 }
 
-// Sum of the 10 statistics over the P adjacent lanes of a slot.
-template <int P>
+// Sum of the first NS statistics over the P adjacent lanes of a slot.
+template <int P, int NS = kNStat>
 __device__ __forceinline__ void subset_sum(float *a) {
 #pragma unroll
-  for (int j = 0; j < kNStat; ++j) {
+  for (int j = 0; j < NS; ++j) {
     a[j] = dpp_add_xor1(a[j]);
     a[j] = dpp_add_xor2(a[j]);
     a[j] = dpp_add_half_mirror(a[j]);
@@ -987,7 +987,7 @@ __device__ __forceinline__ void cull_begin(const CullLds &L, const float *__rest
 // The tiles first, first + stride, ... < end of one frame: cull, E-phase,
 // normaliser, M-phase into L.acc; lse sums into Lacc, active pairs into
 // npairs (thread 0).
-template <int BLOCK, int T, int TRIP, int SCAP, bool CPR, bool LAB>
+template <int BLOCK, int T, int TRIP, int SCAP, bool CPR, bool LAB, bool MEANS = false>
 __device__ __forceinline__ void cull_tiles(
     const CullLds &L, const float4 *__restrict__ pts, const float4 *__restrict__ sph,
     const float *__restrict__ cpar, const float4 *__restrict__ shift, int K, int mode,
@@ -1202,21 +1202,25 @@ __device__ __forceinline__ void cull_tiles(
               const float w0 = gm * d0, w1 = gm * d1, w2 = gm * d2;
               av[0] += gm;
               av[1] += w0; av[2] += w1; av[3] += w2;
-              av[4] = fmaf(w0, d0, av[4]);
-              av[5] = fmaf(w1, d0, av[5]);
-              av[6] = fmaf(w1, d1, av[6]);
-              av[7] = fmaf(w2, d0, av[7]);
-              av[8] = fmaf(w2, d1, av[8]);
-              av[9] = fmaf(w2, d2, av[9]);
+              if constexpr (!MEANS) {
+                av[4] = fmaf(w0, d0, av[4]);
+                av[5] = fmaf(w1, d0, av[5]);
+                av[6] = fmaf(w1, d1, av[6]);
+                av[7] = fmaf(w2, d0, av[7]);
+                av[8] = fmaf(w2, d1, av[8]);
+                av[9] = fmaf(w2, d2, av[9]);
+              }
             }
-            subset_sum<P>(av);
+            // MEANS: the first pass of two-pass moments needs N and S1 only
+            constexpr int NS = MEANS ? 4 : kNStat;
+            subset_sum<P, NS>(av);
             // lane q adds statistic q (and q + 8 when P = 8)
             float u0 = av[0];
 #pragma unroll
-            for (int j = 1; j < kNStat; ++j) u0 = (q == j) ? av[j] : u0;
+            for (int j = 1; j < NS; ++j) u0 = (q == j) ? av[j] : u0;
             double *ab = acc + (size_t)b * kNStat;
-            if (q < kNStat) ab[q] += (double)u0;
-            if (P == 8 && q < 2) ab[q + 8] += (double)(q == 0 ? av[8] : av[9]);
+            if (q < NS) ab[q] += (double)u0;
+            if (!MEANS && P == 8 && q < 2) ab[q + 8] += (double)(q == 0 ? av[8] : av[9]);
           }
         }
       }
@@ -1292,8 +1296,10 @@ __device__ __forceinline__ void cull_end(const CullLds &L, double *__restrict__ 
 // One tile pass of a single frame, grid-strided over the tiles.  LAB: the
 // label pass (one-hot responsibilities from the staged labels; the active
 // list of a tile is the set of its labels), a separate instantiation so
-// that the soft passes carry none of its code.
-template <int BLOCK, int T, int TRIP, int SCAP, bool CPR, bool LAB>
+// that the soft passes carry none of its code.  MEANS: a soft pass that
+// accumulates N and S1 only (the first pass of two-pass moments; the
+// second-moment columns stay zero).
+template <int BLOCK, int T, int TRIP, int SCAP, bool CPR, bool LAB, bool MEANS>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
     const float4 *__restrict__ pts,    // staged (x, y, z, tag), ntiles * T
@@ -1308,8 +1314,9 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
   cull_begin<BLOCK, CPR>(L, cpar, shift, a.K);
   double Lacc = 0.0;
   unsigned long long npairs = 0;
-  cull_tiles<BLOCK, T, TRIP, SCAP, CPR, LAB>(L, pts, sph, cpar, shift, a.K, a.mode, blockIdx.x,
-                                         a.ntiles, gridDim.x, lse_out, Lacc, npairs);
+  cull_tiles<BLOCK, T, TRIP, SCAP, CPR, LAB, MEANS>(L, pts, sph, cpar, shift, a.K, a.mode,
+                                                   blockIdx.x, a.ntiles, gridDim.x, lse_out,
+                                                   Lacc, npairs);
   cull_end<BLOCK>(L, part + (size_t)blockIdx.x * a.ncols, a.K, a.mode, Lacc);
   if (threadIdx.x == 0 && a.pairs) atomicAdd(a.pairs, npairs);
 }

@@ -410,15 +410,16 @@ struct CullCfg {
   using Launch = void (*)(const CullCfg &, hipStream_t, const float4 *, const float4 *,
                           const float *, const float4 *, double *, float *,
                           const TileArgs &);
-  Launch launch = nullptr;      // soft passes
-  Launch launch_lab = nullptr;  // label passes
+  Launch launch = nullptr;        // soft passes
+  Launch launch_lab = nullptr;    // label passes
+  Launch launch_means = nullptr;  // soft passes for N and S1 only
 };
 
-template <int BLOCK, int T, int TRIP, int SCAP, bool CPR, bool LAB>
+template <int BLOCK, int T, int TRIP, int SCAP, bool CPR, bool LAB, bool MEANS>
 void launch_cull(const CullCfg &c, hipStream_t s, const float4 *pts,
                  const float4 *sph, const float *cpar, const float4 *shift,
                  double *part, float *lse, const TileArgs &a) {
-  hipLaunchKernelGGL((em_cull_kernel<BLOCK, T, TRIP, SCAP, CPR, LAB>), dim3(c.grid),
+  hipLaunchKernelGGL((em_cull_kernel<BLOCK, T, TRIP, SCAP, CPR, LAB, MEANS>), dim3(c.grid),
                      dim3(BLOCK), c.lds, s, pts, sph, cpar, shift, part, lse, a);
 }
 
@@ -429,15 +430,16 @@ bool make_cull_cfg(int K, int64_t n, CullCfg *out) {
   const size_t lds = cull_lds_bytes<BLOCK, T, TRIP, SCAP, CPR>(K);
   if (lds > (di.lds_max ? di.lds_max : 65536)) return false;
   const void *fn =
-      reinterpret_cast<const void *>(&em_cull_kernel<BLOCK, T, TRIP, SCAP, CPR, false>);
+      reinterpret_cast<const void *>(&em_cull_kernel<BLOCK, T, TRIP, SCAP, CPR, false, false>);
   const void *fl =
-      reinterpret_cast<const void *>(&em_cull_kernel<BLOCK, T, TRIP, SCAP, CPR, true>);
-  if (lds > 65536 &&
-      (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-           hipSuccess ||
-       hipFuncSetAttribute(fl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-           hipSuccess))
-    return false;
+      reinterpret_cast<const void *>(&em_cull_kernel<BLOCK, T, TRIP, SCAP, CPR, true, false>);
+  const void *fm =
+      reinterpret_cast<const void *>(&em_cull_kernel<BLOCK, T, TRIP, SCAP, CPR, false, true>);
+  if (lds > 65536)
+    for (const void *f : {fn, fl, fm})
+      if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+          hipSuccess)
+        return false;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BLOCK, lds) !=
           hipSuccess || per_cu <= 0)
@@ -448,8 +450,9 @@ bool make_cull_cfg(int K, int64_t n, CullCfg *out) {
   out->trip = TRIP;
   out->grid = (int)std::min<int64_t>(ntiles, (int64_t)di.cus * per_cu);
   out->lds = lds;
-  out->launch = &launch_cull<BLOCK, T, TRIP, SCAP, CPR, false>;
-  out->launch_lab = &launch_cull<BLOCK, T, TRIP, SCAP, CPR, true>;
+  out->launch = &launch_cull<BLOCK, T, TRIP, SCAP, CPR, false, false>;
+  out->launch_lab = &launch_cull<BLOCK, T, TRIP, SCAP, CPR, true, false>;
+  out->launch_means = &launch_cull<BLOCK, T, TRIP, SCAP, CPR, false, true>;
   return true;
 }
 
@@ -711,7 +714,9 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   }
   for (int rep = 0; rep < (timed ? g_prof.reps : 1); ++rep) {
     if (cull)
-      (mode == kLabels ? r.cc.launch_lab : r.cc.launch)(
+      (mode == kLabels                                  ? r.cc.launch_lab
+       : mode == kSoftStats && umode == kUpdMeanOnly ? r.cc.launch_means
+                                                     : r.cc.launch)(
                   r.cc, r.s, at<float4>(r.ws, L.pts4), at<float4>(r.ws, L.tsph),
                   at<float>(r.ws, L.cpar[r.cur]), at<float4>(r.ws, L.shift[r.cur]),
                   at<double>(r.ws, L.part), lse, a);
