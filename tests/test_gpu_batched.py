@@ -169,3 +169,37 @@ def test_batched_culled_against_oracle(monkeypatch):
         assert _rel(r.means.cpu().numpy(), mur) <= 1e-5
         assert _rel(r.covariances.cpu().numpy(), covr) <= 1e-5
         assert abs(r.loglik[0].item() - L0) <= 1e-5 * max(abs(L0), X.shape[0])
+
+
+def test_batched_full_size_bench_workload():
+    """The benchmark's batched workload itself (64 frames, N_f in [20k,
+    300k], K_f in [16, 200], T = 20, one gmm_fit_batched call): every
+    frame's final log-likelihood agrees with its own gmm_fit (any size),
+    and three frames (the smallest, the largest N_f, the largest K_f) with
+    the FP64 oracle."""
+    print("case: batched bench workload 64 frames T=20", flush=True)
+    frames = synth.batched_frames()
+    T = 20
+    labs = [synth.kmeanspp_labels(X, k, 1) for X, k in frames]
+    pts = [_to(X) for X, _ in frames]
+    ks = [k for _, k in frames]
+    res = gmm.fit_batched(pts, ks, iters=T,
+                          labels_list=[_to(l, torch.int32) for l in labs])
+    torch.cuda.synchronize()
+    for i, (p, k, l, r) in enumerate(zip(pts, ks, labs, res)):
+        single = gmm.fit(p, k, iters=T, labels=_to(l, torch.int32))
+        torch.cuda.synchronize()
+        Lb = r.loglik.cpu().numpy()
+        Ls = single.loglik.cpu().numpy()
+        assert np.all(np.isfinite(Lb)), i
+        assert abs(Lb[-1] - Ls[-1]) <= 1e-4 * max(abs(Ls[-1]), p.shape[0]), i
+        assert abs(float(r.weights.sum()) - 1.0) <= 1e-5, i
+    ns = [X.shape[0] for X, _ in frames]
+    pick = sorted({int(np.argmin(ns)), int(np.argmax(ns)), int(np.argmax(ks))})
+    for i in pick:
+        X, k = frames[i]
+        Lr = oracle.fit(X, k, 1e-3, T, labels=labs[i])[3]
+        Lb = res[i].loglik.cpu().numpy()
+        err = np.abs(Lb - Lr) / np.maximum(np.abs(Lr), X.shape[0])
+        print("frame", i, X.shape[0], k, err.max(), flush=True)
+        assert err.max() <= 1e-4
