@@ -793,10 +793,10 @@ __host__ __device__ constexpr size_t cull_lds_bytes(int K) {
          (size_t)S::XS * sizeof(float4) +
          (CPR ? (size_t)0 : (size_t)K * sizeof(float4)) +
          (CPR ? (size_t)0 : (size_t)((K + 63) / 64) * 64 * 3 * sizeof(float4)) +
-         (size_t)K * kNStat * sizeof(double) + 16 * sizeof(uint64_t) +
+         (size_t)K * kNStat * sizeof(double) + 32 * sizeof(uint64_t) +
          (size_t)S::W * sizeof(uint64_t) + (size_t)S::NW * sizeof(double) +
          (size_t)T * sizeof(float2) + (size_t)S::R * T * sizeof(float) +
-         (size_t)K * sizeof(int) + 16;
+         (size_t)2 * K * sizeof(uint16_t) + 16;
 }
 
 // Bounding sphere of every tile of tpts staged points: (centre, radius),
@@ -932,13 +932,13 @@ struct CullLds {
   float4 *ShL;       // K shifts (none if CPR)
   float4 *CP;        // cull parameters, 3 float4 per component, 64-padded
   double *acc;       // K x 10 FP64 sums
-  uint64_t *masks;   // 16
+  uint64_t *masks;   // 2 x 16 (double-buffered: this tile's, the next)
   uint64_t *fbmask;  // W
   double *wL;        // NW
   float2 *fbv;       // T
   float *reds;       // R x T
-  int *list;         // K
-  int *nact_s;       // 1
+  uint16_t *list;    // 2 x K component indices (K <= 1024)
+  int *nact_s;       // 2
 };
 
 template <int BLOCK, int T, int TRIP, int SCAP, bool CPR>
@@ -953,12 +953,12 @@ __device__ __forceinline__ CullLds cull_carve(unsigned char *smem, int K) {
   L.CP = L.ShL + (CPR ? 0 : K);
   L.acc = reinterpret_cast<double *>(L.CP + (size_t)nchk * 64 * 3);
   L.masks = reinterpret_cast<uint64_t *>(L.acc + (size_t)K * kNStat);
-  L.fbmask = L.masks + 16;
+  L.fbmask = L.masks + 32;
   L.wL = reinterpret_cast<double *>(L.fbmask + S::W);
   L.fbv = reinterpret_cast<float2 *>(L.wL + S::NW);
   L.reds = reinterpret_cast<float *>(L.fbv + T);
-  L.list = reinterpret_cast<int *>(L.reds + S::R * T);
-  L.nact_s = L.list + K;
+  L.list = reinterpret_cast<uint16_t *>(L.reds + S::R * T);
+  L.nact_s = reinterpret_cast<int *>(L.list + 2 * K);  // 2K uint16: 4-byte aligned
   return L;
 }
 
@@ -967,7 +967,7 @@ template <int BLOCK, bool CPR>
 __device__ __forceinline__ void cull_begin(const CullLds &L, const float *__restrict__ cpar,
                                            const float4 *__restrict__ shift, int K) {
   const int tid = threadIdx.x;
-  if (tid < 16) L.masks[tid] = 0;  // label passes OR into them
+  if (tid < 32) L.masks[tid] = 0;  // label passes OR into them
   for (int b = tid; b < K; b += BLOCK) {
     if (!CPR) L.ShL[b] = shift[b];
     for (int j = 0; j < kNStat; ++j) L.acc[(size_t)b * kNStat + j] = 0.0;
@@ -1006,7 +1006,7 @@ __device__ __forceinline__ void cull_tiles(
   uint64_t *fbmask = L.fbmask;
   float2 *fbv = L.fbv;
   float *reds = L.reds;
-  int *list = L.list;
+  uint16_t *list = L.list;
   int *nact_s = L.nact_s;
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -1026,7 +1026,7 @@ __device__ __forceinline__ void cull_tiles(
   // label passes: the components of a tile are the labels of its points
   // (masks zero beforehand; OR is order-free, so the list is deterministic).
   // One replica of the points; per wave one LDS OR per distinct label.
-  auto mark_label = [&](float4 xq) {
+  auto mark_label = [&](float4 xq, uint64_t *mk) {
     if (rr != 0) return;
     const int tg = __float_as_int(xq.w);
     bool todo = tg >= 0;
@@ -1037,31 +1037,36 @@ __device__ __forceinline__ void cull_tiles(
       const int t0 = __shfl(tg, first, 64);
       if (todo && tg == t0) todo = false;
       if (lane == first)
-        atomicOr(reinterpret_cast<unsigned long long *>(masks + (t0 >> 6)), 1ull << (t0 & 63));
+        atomicOr(reinterpret_cast<unsigned long long *>(mk + (t0 >> 6)), 1ull << (t0 & 63));
     }
   };
 
-  // active list of a tile from the masks: wave w < nchk places chunk w
-  auto build_list = [&]() {
-    if (w < nchk) {
+  // active list of a tile from masks buffer bf: chunk c is placed by wave
+  // W + c when the block has that many waves (the waves of the first
+  // replica are busy with the normaliser meanwhile), else by wave c
+  const int wl = (NW >= W + nchk) ? w - W : w;
+  auto build_list = [&](int bf) {
+    const uint64_t *mk = masks + 16 * bf;
+    if (wl >= 0 && wl < nchk) {
       int off = 0;
-      for (int c = 0; c < w; ++c) off += __popcll(masks[c]);
-      const uint64_t m = masks[w];
+      for (int c = 0; c < wl; ++c) off += __popcll(mk[c]);
+      const uint64_t m = mk[wl];
       const unsigned below = __builtin_amdgcn_mbcnt_hi(
           (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-      if ((m >> lane) & 1ull) list[off + (int)below] = (w << 6) + lane;
-      if (w == nchk - 1 && lane == 0) *nact_s = off + __popcll(m);
+      if ((m >> lane) & 1ull) list[K * bf + off + (int)below] = (uint16_t)((wl << 6) + lane);
+      if (wl == nchk - 1 && lane == 0) nact_s[bf] = off + __popcll(m);
     }
   };
 
-  // first tile: masks, list; the point and sphere of the next tile ahead
+  // first tile: masks, list (buffer 0); the point and sphere of the next tile
   int tile = first;
+  int cur = 0;
   float4 xn = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
   float4 spn = make_float4(0.f, 0.f, 0.f, -1.0f);
   if (tile < end) {
     xn = pts[(size_t)tile * T + t];
     if constexpr (LAB) {
-      mark_label(xn);
+      mark_label(xn, masks);
     } else {
       if (w < nchk) {
         const uint64_t m = cull_mask(sph[tile]);
@@ -1071,95 +1076,111 @@ __device__ __forceinline__ void cull_tiles(
     }
   }
   __syncthreads();
-  if (tile < end) build_list();
+  if (tile < end) build_list(0);
   __syncthreads();
 
+  // Per tile three barriers: (E-phase + cull of the next tile) | A |
+  // (normaliser + list of the next tile) | B | (M-phase [+ far points]) | C.
+  // Masks and lists are double-buffered: `cur` is this tile's, `nxt` the
+  // next tile's.
   for (; tile < end; tile += stride) {
     const float4 x = xn;
-    if (tile + stride < end) xn = pts[(size_t)(tile + stride) * T + t];
+    const bool more = tile + stride < end;
+    if (more) xn = pts[(size_t)(tile + stride) * T + t];
     const bool valid = __float_as_int(x.w) >= 0;
-    const int nact = *nact_s;
+    const int nxt = cur ^ 1;
+    const int nact = nact_s[cur];
+    const uint16_t *lst = list + K * cur;
 
     if constexpr (LAB) {
       // ---- one-hot rows of the first SCAP slots; weight 1 per point
-      if (tid < 16) masks[tid] = 0;
       const int tg = __float_as_int(x.w);
       for (int sl = rr; sl < min(nact, SCAP); sl += R)
-        E[sl * RS + tx] = (__builtin_amdgcn_readfirstlane(list[sl]) == tg) ? 1.0f : 0.0f;
+        E[sl * RS + tx] = (__builtin_amdgcn_readfirstlane((int)lst[sl]) == tg) ? 1.0f : 0.0f;
       if (rr == 0) {
         Xs[tx] = make_float4(x.x, x.y, x.z, valid ? 1.0f : 0.0f);
         fbv[t] = make_float2(__int_as_float(tg), 0.0f);
         if (lane == 0) fbmask[pg] = 0;
       }
-      __syncthreads();
+      // labels of the next tile (its mask buffer was cleared a tile ago)
+      if (more) mark_label(xn, masks + 16 * nxt);
+      __syncthreads();                                              // A
     } else {
-    // ---- E-phase: slots rr, rr + R, ... of the active list, EU at a time
-    float s = 0.0f;
-    {
-      constexpr int EU = GMM_CULL_EU;
-      int sl = rr;
-      for (; sl + (EU - 1) * R < nact; sl += EU * R) {
-        float e[EU];
+      // ---- E-phase: slots rr, rr + R, ... of the active list, EU at a time
+      float s = 0.0f;
+      {
+        constexpr int EU = GMM_CULL_EU;
+        int sl = rr;
+        for (; sl + (EU - 1) * R < nact; sl += EU * R) {
+          float e[EU];
 #pragma unroll
-        for (int u = 0; u < EU; ++u) {
-          const int b = __builtin_amdgcn_readfirstlane(list[sl + u * R]);
-          e[u] = __builtin_amdgcn_exp2f(
-              comp_logterm(cpar + (size_t)b * kParStride, x.x, x.y, x.z));
+          for (int u = 0; u < EU; ++u) {
+            const int b = __builtin_amdgcn_readfirstlane((int)lst[sl + u * R]);
+            e[u] = __builtin_amdgcn_exp2f(
+                comp_logterm(cpar + (size_t)b * kParStride, x.x, x.y, x.z));
+          }
+#pragma unroll
+          for (int u = 0; u < EU; ++u) s += e[u];
+          if (sl + (EU - 1) * R < SCAP) {
+#pragma unroll
+            for (int u = 0; u < EU; ++u) E[(sl + u * R) * RS + tx] = e[u];
+          } else {
+#pragma unroll
+            for (int u = 0; u < EU - 1; ++u)
+              if (sl + u * R < SCAP) E[(sl + u * R) * RS + tx] = e[u];
+          }
         }
-#pragma unroll
-        for (int u = 0; u < EU; ++u) s += e[u];
-        if (sl + (EU - 1) * R < SCAP) {
-#pragma unroll
-          for (int u = 0; u < EU; ++u) E[(sl + u * R) * RS + tx] = e[u];
-        } else {
-#pragma unroll
-          for (int u = 0; u < EU - 1; ++u)
-            if (sl + u * R < SCAP) E[(sl + u * R) * RS + tx] = e[u];
+        for (; sl < nact; sl += R) {
+          const int b0 = __builtin_amdgcn_readfirstlane((int)lst[sl]);
+          const float e0 = __builtin_amdgcn_exp2f(
+              comp_logterm(cpar + (size_t)b0 * kParStride, x.x, x.y, x.z));
+          s += e0;
+          if (sl < SCAP) E[sl * RS + tx] = e0;
         }
       }
-      for (; sl < nact; sl += R) {
-        const int b0 = __builtin_amdgcn_readfirstlane(list[sl]);
-        const float e0 = __builtin_amdgcn_exp2f(
-            comp_logterm(cpar + (size_t)b0 * kParStride, x.x, x.y, x.z));
-        s += e0;
-        if (sl < SCAP) E[sl * RS + tx] = e0;
+      reds[rr * T + t] = s;
+      // ---- cull of the next tile
+      if (more && w < nchk) {
+        const uint64_t m = cull_mask(spn);
+        if (lane == 0) masks[16 * nxt + w] = m;
       }
-    }
-    reds[rr * T + t] = s;
-    __syncthreads();
+      if (tile + 2 * stride < end) spn = sph[tile + 2 * stride];
+      __syncthreads();                                              // A
 
-    // ---- normaliser (waves of the first replica: one thread per point)
-    if (rr == 0) {
-      float st = reds[t];
+      // ---- normaliser (waves of the first replica: one thread per point)
+      if (rr == 0) {
+        float st = reds[t];
 #pragma unroll
-      for (int j = 1; j < R; ++j) st += reds[j * T + t];
-      const bool fb = valid && !(st >= 0x1p-100f);
-      float mref = 0.0f;
-      if (fb) {
-        // far from every component: own maximum over all K (as the dense
-        // kernel's fallback); the point joins the statistics afterwards
-        float mx = -INFINITY;
-        for (int bb = 0; bb < K; ++bb)
-          mx = fmaxf(mx, comp_logterm(cpar + (size_t)bb * kParStride, x.x, x.y, x.z));
-        st = 0.0f;
-        for (int bb = 0; bb < K; ++bb)
-          st += __builtin_amdgcn_exp2f(
-              comp_logterm(cpar + (size_t)bb * kParStride, x.x, x.y, x.z) - mx);
-        mref = mx;
-        fbv[t] = make_float2(mx, st);
-      }
-      Xs[tx] = make_float4(x.x, x.y, x.z,
-                           (valid && !fb) ? __builtin_amdgcn_rcpf(st) : 0.0f);
-      const uint64_t fm = __ballot(fb);
-      if (lane == 0) fbmask[pg] = fm;
-      if (valid) {
-        const double lse = (Cb + (double)mref + (double)__builtin_amdgcn_logf(st)) * kLn2;
-        Lacc += lse;
-        if (lse_out) lse_out[(size_t)tile * T + t] = (float)lse;
+        for (int j = 1; j < R; ++j) st += reds[j * T + t];
+        const bool fb = valid && !(st >= 0x1p-100f);
+        float mref = 0.0f;
+        if (fb) {
+          // far from every component: own maximum over all K (as the dense
+          // kernel's fallback); the point joins the statistics afterwards
+          float mx = -INFINITY;
+          for (int bb = 0; bb < K; ++bb)
+            mx = fmaxf(mx, comp_logterm(cpar + (size_t)bb * kParStride, x.x, x.y, x.z));
+          st = 0.0f;
+          for (int bb = 0; bb < K; ++bb)
+            st += __builtin_amdgcn_exp2f(
+                comp_logterm(cpar + (size_t)bb * kParStride, x.x, x.y, x.z) - mx);
+          mref = mx;
+          fbv[t] = make_float2(mx, st);
+        }
+        Xs[tx] = make_float4(x.x, x.y, x.z,
+                             (valid && !fb) ? __builtin_amdgcn_rcpf(st) : 0.0f);
+        const uint64_t fm = __ballot(fb);
+        if (lane == 0) fbmask[pg] = fm;
+        if (valid) {
+          const double lse = (Cb + (double)mref + (double)__builtin_amdgcn_logf(st)) * kLn2;
+          Lacc += lse;
+          if (lse_out) lse_out[(size_t)tile * T + t] = (float)lse;
+        }
       }
     }
-    __syncthreads();
-    }
+    // ---- active list of the next tile
+    if (more) build_list(nxt);
+    __syncthreads();                                                // B
 
     // ---- M-phase over the active list, SCAP slots at a time
     if (tid == 0) npairs += (unsigned)nact;
@@ -1172,7 +1193,7 @@ __device__ __forceinline__ void cull_tiles(
           __syncthreads();
           for (int u = w; u < nloc * W; u += NW) {
             const int sl = u / W, g2 = u % W;
-            const int b = __builtin_amdgcn_readfirstlane(list[c0 + sl]);
+            const int b = __builtin_amdgcn_readfirstlane((int)lst[c0 + sl]);
             const int t2 = g2 * 64 + lane, c2 = t2 + t2 / TRIP;
             if constexpr (LAB) {
               E[sl * RS + c2] = (__float_as_int(fbv[t2].x) == b) ? 1.0f : 0.0f;
@@ -1187,7 +1208,7 @@ __device__ __forceinline__ void cull_tiles(
         for (int s0 = 0; s0 < nloc; s0 += SLOTS) {
           const int sl = s0 + tid / P;
           if (sl < nloc) {
-            const int b = list[c0 + sl];
+            const int b = lst[c0 + sl];
             const float4 sh = ShL[b];
             const float *Eb = E + sl * RS + q * (TRIP + 1);
             const float4 *Xb = Xs + q * (TRIP + 1);
@@ -1225,48 +1246,46 @@ __device__ __forceinline__ void cull_tiles(
         }
       }
     }
-    // ---- cull of the next tile
-    const bool more = tile + stride < end;
-    if constexpr (LAB) {
-      if (more) mark_label(xn);
-    } else {
-      if (more && w < nchk) {
-        const uint64_t m = cull_mask(spn);
-        if (lane == 0) masks[w] = m;
-      }
-      if (tile + 2 * stride < end) spn = sph[tile + 2 * stride];
-    }
-    __syncthreads();
 
-    // ---- far points of this tile (rare): wave 0, one lane per component
-    if (mode != kSoftLogLik && w == 0) {
-      for (int g2 = 0; g2 < W; ++g2) {
-        uint64_t fm = fbmask[g2];
-        while (fm) {
-          const int i = __builtin_ctzll(fm);
-          fm &= fm - 1;
-          const int t2 = g2 * 64 + i;
-          const float4 xp = Xs[t2 + t2 / TRIP];
-          const float2 v = fbv[t2];
-          const float inv = __builtin_amdgcn_rcpf(v.y);
-          for (int b = lane; b < K; b += 64) {
-            const float gm = __builtin_amdgcn_exp2f(
-                comp_logterm(cpar + (size_t)b * kParStride, xp.x, xp.y, xp.z) - v.x) * inv;
-            const float4 sh = ShL[b];
-            const float d0 = xp.x - sh.x, d1 = xp.y - sh.y, d2 = xp.z - sh.z;
-            double *ab = acc + (size_t)b * kNStat;
-            ab[0] += (double)gm;
-            ab[1] += (double)(gm * d0); ab[2] += (double)(gm * d1); ab[3] += (double)(gm * d2);
-            ab[4] += (double)(gm * d0 * d0); ab[5] += (double)(gm * d1 * d0);
-            ab[6] += (double)(gm * d1 * d1); ab[7] += (double)(gm * d2 * d0);
-            ab[8] += (double)(gm * d2 * d1); ab[9] += (double)(gm * d2 * d2);
+    // ---- far points of this tile (rare): wave 0, one lane per component,
+    // after the M-phase's updates of the same sums
+    bool anyfb = false;
+#pragma unroll
+    for (int g2 = 0; g2 < W; ++g2) anyfb = anyfb || fbmask[g2] != 0;
+    if (mode != kSoftLogLik && anyfb) {
+      __syncthreads();
+      if (w == 0) {
+        for (int g2 = 0; g2 < W; ++g2) {
+          uint64_t fm = fbmask[g2];
+          while (fm) {
+            const int i = __builtin_ctzll(fm);
+            fm &= fm - 1;
+            const int t2 = g2 * 64 + i;
+            const float4 xp = Xs[t2 + t2 / TRIP];
+            const float2 v = fbv[t2];
+            const float inv = __builtin_amdgcn_rcpf(v.y);
+            for (int b = lane; b < K; b += 64) {
+              const float gm = __builtin_amdgcn_exp2f(
+                  comp_logterm(cpar + (size_t)b * kParStride, xp.x, xp.y, xp.z) - v.x) * inv;
+              const float4 sh = ShL[b];
+              const float d0 = xp.x - sh.x, d1 = xp.y - sh.y, d2 = xp.z - sh.z;
+              double *ab = acc + (size_t)b * kNStat;
+              ab[0] += (double)gm;
+              ab[1] += (double)(gm * d0); ab[2] += (double)(gm * d1); ab[3] += (double)(gm * d2);
+              ab[4] += (double)(gm * d0 * d0); ab[5] += (double)(gm * d1 * d0);
+              ab[6] += (double)(gm * d1 * d1); ab[7] += (double)(gm * d2 * d0);
+              ab[8] += (double)(gm * d2 * d1); ab[9] += (double)(gm * d2 * d2);
+            }
           }
         }
       }
     }
-    // ---- active list of the next tile
-    if (more) build_list();
-    __syncthreads();
+    // label passes: this tile's mask buffer is marked again two tiles on
+    if constexpr (LAB) {
+      if (tid < 16) masks[16 * cur + tid] = 0;
+    }
+    __syncthreads();                                                // C
+    cur = nxt;
   }
 }
 
