@@ -106,6 +106,13 @@ gmm_status gmm_workspace_status(const void *ws, void *stream);
  *  mu_b = sum_n g_nb x_n / N_b,
  *  Sigma_b = sum_n g_nb (x_n - mu_b)(x_n - mu_b)^T / N_b + lambda I
  *  (FP64 sums), then an FP64 Cholesky of each Sigma_b for the next E-step.
+ *  Internally the staged copy of the points is put in Morton (Z-curve)
+ *  order and the E-step skips every (tile of points, component) pair
+ *  whose FP32 weights, by a bound over the tile's bounding sphere, are
+ *  exactly zero for all of the tile's points, so the results equal the
+ *  dense evaluation up to the order of FP32 additions; the caller's arrays are not reordered, and repeated calls
+ *  with the same inputs give bitwise identical results.  GMM_CULL=0 or
+ *  GMM_SORT=0 in the environment switch the skipping or the ordering off.
  *  Synchronises `stream` once at the end unless GMM_FLAG_ASYNC is set.
  *  Errors: INVALID_ARG (sizes, NULL pointers, options), UNSUPPORTED
  *  (K > GMM_MAX_K), OOM (workspace), then device-side NOT_SPD / NONFINITE /
