@@ -20,9 +20,10 @@
 // operation rounded on its own (no contraction).
 //
 // Per round j >= 1: kpp_update_kernel (D2 with centre j - 1, chunk totals)
-// and kpp_select_kernel (one block: group totals, W, the search).  All of
-// it is latency-bound bookkeeping (16 B of D2 traffic and ~10 FLOP per
-// point per round), far from any roofline.
+// and kpp_select_kernel (one block: group totals, W, the search).  The
+// update streams 28 B per point per round (the point, D2 read and
+// written); the select kernel is a short chain of dependent reads and
+// serial sums; neither does enough arithmetic to meet a compute roofline.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,7 +31,7 @@
 
 namespace gmm_dev {
 
-constexpr int kKppChunk = 256;      // points per chunk = update block size
+constexpr int kKppChunk = 256;      // points per chunk (running-sum order)
 constexpr int kKppGroup = 64;       // chunks per group
 constexpr int kKppSelThreads = 1024;
 constexpr int kKppLabelThreads = 256;
