@@ -922,7 +922,7 @@ __device__ __forceinline__ uint64_t cull_ballot(const float4 *cp, float4 sp) {
 #define GMM_CULL_WPE 1
 #endif
 #ifndef GMM_CULL_EU
-#define GMM_CULL_EU 4  // E-phase components per step
+#define GMM_CULL_EU 8  // E-phase components per step
 #endif
 
 // LDS of the culled tile loop (carved from the dynamic shared memory).
