@@ -1692,6 +1692,11 @@ gmm_status gmm_kmeanspp(const float *pts, int64_t n, int32_t k, const double *u,
                        n, u, j, centres);
     HIP_TRY(hipGetLastError());
   }
+  if (!labels && k == 1) {  // no distances formed: check the points alone
+    hipLaunchKernelGGL(kpp_check_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       pts, n, status);
+    HIP_TRY(hipGetLastError());
+  }
   if (labels) {
     hipLaunchKernelGGL(kpp_label_kernel,
                        dim3((unsigned)((n + kKppLabelThreads - 1) / kKppLabelThreads)),

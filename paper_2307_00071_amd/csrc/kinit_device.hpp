@@ -318,6 +318,14 @@ __global__ __launch_bounds__(kKppSelThreads) void kpp_select_kernel(
   if (threadIdx.x == 0) cidx[j] = w.idx < 0 ? cidx[j - 1] : ilo + w.idx;
 }
 
+// Non-finite coordinates (for a call that forms no distances otherwise).
+__global__ __launch_bounds__(256) void kpp_check_kernel(const float *__restrict__ pts,
+                                                        int64_t n, uint32_t *status) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n && (!isfinite(pts[3 * i]) || !isfinite(pts[3 * i + 1]) || !isfinite(pts[3 * i + 2])))
+    set_status(status, kStNonFinite);
+}
+
 // label_i = the nearest of the K centres (lowest index on ties).
 __global__ __launch_bounds__(kKppLabelThreads) void kpp_label_kernel(
     const float *__restrict__ pts, int64_t n, const int64_t *__restrict__ cidx, int K,

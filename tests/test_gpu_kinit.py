@@ -130,3 +130,28 @@ def test_kmeanspp_then_fit_matches_oracle():
     Lo = oracle.fit(X, K, 1e-3, T, labels=rl)[3]
     Lg = r.loglik.cpu().numpy()
     assert abs(Lg[-1] - Lo[-1]) <= 1e-4 * max(abs(Lo[-1]), X.shape[0])
+
+
+def test_kmeanspp_without_labels_through_the_abi():
+    """labels = NULL: centres only (equal to the oracle's); with K = 1 the
+    points are still checked for non-finite values."""
+    import ctypes
+    _case("kmeanspp labels NULL")
+    lib = _lib.load()
+    X = _depth_subset(5000, 3)
+    Xt = torch.from_numpy(X).to(DEV)
+    u = np.random.default_rng(4).random(6)
+    ut = torch.from_numpy(u).to(DEV)
+    cen = torch.empty(6, dtype=torch.int64, device=DEV)
+    st = lib.gmm_kmeanspp(ctypes.c_void_p(Xt.data_ptr()), 5000, 6,
+                          ctypes.c_void_p(ut.data_ptr()), ctypes.c_void_p(cen.data_ptr()),
+                          None, None, 0, None)
+    assert st == 0
+    rc, _ = oracle.kmeanspp(X.astype(np.float64), 6, u)
+    np.testing.assert_array_equal(cen.cpu().numpy(), rc)
+    Xn = Xt.clone()
+    Xn[4321, 0] = float("inf")
+    st = lib.gmm_kmeanspp(ctypes.c_void_p(Xn.data_ptr()), 5000, 1,
+                          ctypes.c_void_p(ut.data_ptr()), ctypes.c_void_p(cen.data_ptr()),
+                          None, None, 0, None)
+    assert st == 3
