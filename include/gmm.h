@@ -152,7 +152,10 @@ gmm_status gmm_loglik(const float *pts, int64_t n, const float *pose6,
  *   g_mu     K x 3: Sigma_b^-1 sum_n gamma_nb d_nb;
  *   g_cov    K x 3 x 3: 1/2 Sigma_b^-1 (sum_n gamma_nb d d^T) Sigma_b^-1
  *            - 1/2 N_b Sigma_b^-1 (the symmetric gradient);
- *  with d_nb = y_n - mu_b and N_b = sum_n gamma_nb.  Does not synchronise. */
+ *  with d_nb = y_n - mu_b and N_b = sum_n gamma_nb.  A component whose
+ *  covariance is not SPD sets NOT_SPD in the status word and gets NaN in its
+ *  g_w / g_mu / g_cov entries.  Does not synchronise; device-side errors via
+ *  gmm_workspace_status(). */
 size_t gmm_loglik_backward_workspace_size(int64_t n, int32_t k);
 
 gmm_status gmm_loglik_backward(const float *pts, int64_t n, const float *pose6,

@@ -190,9 +190,22 @@ def _gmm_args(w, mu, cov, dev):
     return w, mu, cov, k
 
 
-def loglik(points, w, mu, cov, pose6=None, return_lse=False):
+def _device_status(ws, dev):
+    """Waits for the stream and raises GmmError when the kernels flagged a
+    device-side condition (non-SPD covariance, weight <= 0, non-finite
+    point or result) in the workspace's status word."""
+    lib = _lib.load()
+    _lib.check(lib.gmm_workspace_status(_ptr(ws), _stream(dev)))
+
+
+def loglik(points, w, mu, cov, pose6=None, return_lse=False, check=True):
     """L = sum_n ln sum_b w_b N(R x_n + t | mu_b, cov_b) (float64 scalar on
-    the device).  pose6 = (omega, t) float32 (6,) or None."""
+    the device).  pose6 = (omega, t) float32 (6,) or None.
+
+    check=True waits for the result and raises GmmError on a device-side
+    error (a covariance that is not SPD, a weight <= 0, a non-finite
+    point); check=False returns without waiting (the result is then
+    unspecified after such an error)."""
     torch = _torch()
     lib = _lib.load()
     pts = _check_points(points)
@@ -210,14 +223,17 @@ def loglik(points, w, mu, cov, pose6=None, return_lse=False):
     _lib.check(lib.gmm_loglik(_ptr(pts), n, _ptr(pose), k, _ptr(w), _ptr(mu),
                               _ptr(cov), _ptr(out), _ptr(lse), _ptr(ws),
                               ws.numel(), _stream(dev)))
+    if check:
+        _device_status(ws, dev)
     return (out, lse) if return_lse else out
 
 
 def loglik_backward(points, w, mu, cov, pose6=None, grad_L=None,
-                    need=("pose", "pts", "w", "mu", "cov")):
+                    need=("pose", "pts", "w", "mu", "cov"), check=True):
     """Gradient of grad_L * L with respect to pose (omega, t), points,
     weights, means and covariances; returns a dict of float32 tensors
-    (None for keys not in ``need``)."""
+    (None for keys not in ``need``).  ``check`` as for loglik (a component
+    whose covariance is not SPD has NaN gradients)."""
     torch = _torch()
     lib = _lib.load()
     pts = _check_points(points)
@@ -241,6 +257,8 @@ def loglik_backward(points, w, mu, cov, pose6=None, grad_L=None,
         _ptr(pts), n, _ptr(pose), k, _ptr(w), _ptr(mu), _ptr(cov), _ptr(gl),
         _ptr(g["pose"]), _ptr(g["pts"]), _ptr(g["w"]), _ptr(g["mu"]),
         _ptr(g["cov"]), _ptr(ws), ws.numel(), _stream(dev)))
+    if check:
+        _device_status(ws, dev)
     return g
 
 

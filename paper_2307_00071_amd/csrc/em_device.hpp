@@ -1958,7 +1958,14 @@ __global__ __launch_bounds__(256) void bwd_finish_kernel(
     const double C[6] = {c[0], c[3], c[4], c[6], c[7], c[8]};
     double L[6], P[6];
     if (!chol3(C, L)) {
+      // no gradient exists: the component's outputs are NaN, not stale memory
       set_status(status, kStNotSpd);
+      const float nan = __builtin_nanf("");
+      if (g_w) g_w[b] = nan;
+      if (g_mu)
+        for (int i = 0; i < 3; ++i) g_mu[3 * b + i] = nan;
+      if (g_cov)
+        for (int i = 0; i < 9; ++i) g_cov[9 * b + i] = nan;
       continue;
     }
     tri_inv3(L, P);

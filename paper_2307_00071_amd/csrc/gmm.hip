@@ -219,7 +219,7 @@ bool make_cfg(int K, int64_t n, TileCfg *out) {
 
 // Launch configuration of the backward kernel (all K components in LDS).
 struct BwdCfg {
-  int block = 0, grid = 0, P = 0, trip = 0;
+  int block = 0, tile = 0, grid = 0, P = 0, trip = 0;
   size_t lds = 0;
   void (*launch)(const BwdCfg &, hipStream_t, const float4 *, const float *,
                  const float4 *, const float *, const double *, double *,
@@ -267,6 +267,7 @@ bool make_bwd_cfg(int K, int64_t n, BwdCfg *out) {
     return false;
   const int64_t ntiles = (n + T - 1) / T;
   out->block = BLOCK;
+  out->tile = T;
   out->grid = (int)std::min<int64_t>(ntiles, (int64_t)di.cus * per_cu);
   out->P = P;
   out->trip = trip;
@@ -1815,8 +1816,10 @@ gmm_status gmm_loglik_backward(const float *pts, int64_t n, const float *pose6,
   }
   if ((st = stage(r, pts, n, nullptr, Rt)) != GMM_OK) return st;
   if ((st = run_precompute(r, w, mu, cov)) != GMM_OK) return st;
+  // the backward kernel has its own tile size (the forward's shape, which a
+  // forced or tuned configuration may set to 128 points, does not apply)
   TileArgs a;
-  a.ntiles = (int)(r.L.npad / r.c.tile);
+  a.ntiles = (int)(r.L.npad / bc.tile);
   a.K = k;
   a.KC = k;
   a.P = bc.P;

@@ -132,3 +132,52 @@ def test_grad_scaling_by_upstream():
     for key in g1:
         np.testing.assert_allclose(g2[key].cpu().numpy(), -3.0 * g1[key].cpu().numpy(),
                                    rtol=1e-6, atol=1e-30)
+
+
+@pytest.mark.parametrize("shape", ["b1024t128", "b512t128"])
+def test_backward_under_forced_128_point_forward_shape(shape, monkeypatch):
+    """The backward kernel tiles by 64 points whatever forward shape is
+    forced or tuned: every point must reach the gradients."""
+    _case("backward with GMM_TILE_SHAPE=%s" % shape)
+    monkeypatch.setenv("GMM_TILE_SHAPE", shape)
+    src, pose, th = _registration_problem(20011, 64, seed=11, fit_n=8000)
+    _check(src, pose, th)
+
+
+def test_device_errors_are_raised_forward_and_backward():
+    """A covariance that is not SPD, a weight <= 0 and a non-finite point are
+    device-side conditions: loglik / loglik_backward raise GmmError with the
+    status, and a failed component's gradients are NaN (not stale memory)."""
+    from paper_2307_00071_amd._lib import GmmError
+    _case("device errors")
+    src, pose, th = _registration_problem(4000, 8, seed=12, fit_n=4000)
+    w, mu, cov = (a.copy() for a in th)
+    bad = cov.copy()
+    bad[3] = np.diag([1.0, -1.0, 1.0]).astype(np.float32)   # indefinite
+    for fn in (lambda c: gmm.loglik(_to(src), _to(w), _to(mu), _to(c), pose6=_to(pose)),
+               lambda c: gmm.loglik_backward(_to(src), _to(w), _to(mu), _to(c),
+                                             pose6=_to(pose))):
+        with pytest.raises(GmmError) as ei:
+            fn(bad)
+        assert ei.value.status == 2, ei.value          # GMM_ERR_NOT_SPD
+    g = gmm.loglik_backward(_to(src), _to(w), _to(mu), _to(bad), pose6=_to(pose),
+                            check=False)
+    torch.cuda.synchronize()
+    for key, shp in (("w", ()), ("mu", (3,)), ("cov", (3, 3))):
+        v = g[key].cpu().numpy()
+        assert np.isnan(v[3]).all(), key
+        assert np.isfinite(np.delete(v, 3, axis=0)).all(), key
+    wneg = w.copy()
+    wneg[1] = 0.0
+    with pytest.raises(GmmError) as ei:
+        gmm.loglik(_to(src), _to(wneg), _to(mu), _to(cov))
+    assert ei.value.status == 1, ei.value              # GMM_ERR_INVALID_ARG
+    nanpts = src.copy()
+    nanpts[17, 1] = np.nan
+    for fn in (lambda: gmm.loglik(_to(nanpts), _to(w), _to(mu), _to(cov)),
+               lambda: gmm.loglik_backward(_to(nanpts), _to(w), _to(mu), _to(cov))):
+        with pytest.raises(GmmError) as ei:
+            fn()
+        assert ei.value.status == 3, ei.value          # GMM_ERR_NONFINITE
+    # a good call on the same process afterwards is unaffected
+    _check(src, pose, th)
