@@ -12,7 +12,7 @@ precision form of the Gaussian log-density); the M-step is the standard
 full-covariance maximum-likelihood update (the paper names it without
 formulas).  ``kmeanspp`` is the k-means++ seeding read into the randomised
 k-means initialisation that precedes EM in the same section (its draws are
-inputs; its running sums follow a fixed chunked order).
+inputs; the draw is turned into an index by one flat running sum).
 """
 from __future__ import annotations
 
@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (FP64, no fast-math, OpenMP)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+        cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp",
                "-fno-fast-math", "-ffp-contract=off", "-Wall", "-Wextra",
                "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
@@ -70,7 +70,12 @@ def _load():
                                            D, D, D, D, D]
         lib.oracle_kmeanspp.argtypes = [i64, D, i32, D,
                                         ctypes.POINTER(ctypes.c_int64), I32]
-        for name in ("oracle_component_terms", "oracle_estep",
+        lib.oracle_nearest.argtypes = [i64, D, i32, ctypes.POINTER(ctypes.c_int64),
+                                       I32]
+        lib.oracle_kmeanspp_replay.argtypes = [
+            i64, D, i32, D, ctypes.POINTER(ctypes.c_int64),
+            ctypes.POINTER(ctypes.c_int64), D, D, D]
+        for name in ("oracle_kmeanspp_replay", "oracle_nearest", "oracle_component_terms", "oracle_estep",
                      "oracle_mstep_labels", "oracle_em_step", "oracle_fit",
                      "oracle_loglik_pose", "oracle_loglik_grad",
                      "oracle_kmeanspp"):
@@ -217,9 +222,9 @@ def loglik_grad(X, pose6, w, mu, cov, grad_L=1.0):
 def kmeanspp(X, K, u):
     """k-means++ D^2 seeding with the K uniform draws u (in [0, 1)) given,
     and nearest-seed labels (ties to the lowest index).  Returns
-    (centre indices int64 (K,), labels int32 (N,)).  The running sums that
-    turn a draw into an index follow a fixed order (chunks of 256 points,
-    groups of 64 chunks); see oracle_kmeanspp in gmm_oracle.c."""
+    (centre indices int64 (K,), labels int32 (N,)).  Centre j >= 1 is the
+    first index whose flat running sum of D^2 (in index order, double
+    precision) exceeds u[j] * W; see oracle_kmeanspp in gmm_oracle.c."""
     X = _f64(X).reshape(-1, 3)
     u = _f64(u)
     K = int(K)
@@ -232,3 +237,37 @@ def kmeanspp(X, K, u):
         N, _d(X), K, _d(u), cen.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
         lab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     return cen, lab
+
+
+def nearest(X, centres):
+    """Hard labels: for each point the index j of the nearest centre
+    X[centres[j]] (squared distance ((dx^2 + dy^2) + dz^2) in double, the
+    lowest j on ties).  Returns int32 (N,)."""
+    X = _f64(X).reshape(-1, 3)
+    cen = np.ascontiguousarray(np.asarray(centres, dtype=np.int64))
+    lab = np.zeros(X.shape[0], dtype=np.int32)
+    _check(_load().oracle_nearest(
+        X.shape[0], _d(X), int(cen.shape[0]),
+        cen.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        lab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return lab
+
+
+def kmeanspp_replay(X, u, centres):
+    """Replays the seeding `centres` (K indices) with draws u: per step j the
+    flat running-sum pick on that trajectory (int64 (K,)), and the total W
+    and the running sums before and at centres[j] as double-double (hi, lo)
+    pairs (three float64 (K, 2) arrays; row 0 unused)."""
+    X = _f64(X).reshape(-1, 3)
+    u = _f64(u)
+    cen = np.ascontiguousarray(np.asarray(centres, dtype=np.int64))
+    K = int(cen.shape[0])
+    if u.shape != (K,):
+        raise OracleError("need K uniform draws")
+    flat = np.zeros(K, dtype=np.int64)
+    W, lo, at = np.zeros((K, 2)), np.zeros((K, 2)), np.zeros((K, 2))
+    p64 = ctypes.POINTER(ctypes.c_int64)
+    _check(_load().oracle_kmeanspp_replay(
+        X.shape[0], _d(X), K, _d(u), cen.ctypes.data_as(p64),
+        flat.ctypes.data_as(p64), _d(W), _d(lo), _d(at)))
+    return flat, W, lo, at

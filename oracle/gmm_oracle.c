@@ -568,50 +568,44 @@ int oracle_loglik_grad(int64_t N, const double *X, const double *pose6, int K,
  *   centre 0: index floor(u[0] * N) (at most N - 1);
  *   D2_i = squared distance from x_i to the nearest centre chosen so far;
  *   centre j >= 1: with W = sum_i D2_i and t = u[j] * W, the first index
- *     whose running sum of D2 exceeds t (so index i is drawn with
- *     probability D2_i / W); if W = 0 every point is a centre already and
- *     centre j repeats centre j - 1;
+ *     whose running sum D2_0 + ... + D2_i exceeds t (so index i is drawn
+ *     with probability D2_i / W); if W = 0 every point is a centre already
+ *     and centre j repeats centre j - 1;
  *   label_i = index j of the nearest centre (the lowest j on ties).
  *
- * Because a floating-point running sum depends on its order, the order is
- * fixed: D2 is summed sequentially within chunks of KPP_CHUNK points, the
- * chunk totals sequentially within groups of KPP_GROUP chunks, and the
- * group totals sequentially; the search walks groups, then the chunks of
- * the chosen group, then the points of the chosen chunk, each time
- * comparing the running sum with what is left of t.  Squared distances are
- * ((dx^2 + dy^2) + dz^2) in double with every operation rounded on its own
- * (the file is compiled without contraction). */
-#define KPP_CHUNK 256
-#define KPP_GROUP 64
-
+ * This is the definition written out: one flat running sum over the points
+ * in index order, in double precision, and W is its last value.  When
+ * rounding leaves no running sum above t (t within an ulp of W), the pick is
+ * the last point with D2 > 0.  Squared distances are ((dx^2 + dy^2) + dz^2)
+ * in double with every operation rounded on its own (the file is compiled
+ * without contraction). */
 static double kpp_d2(const double *a, const double *b) {
   const double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
   return (d0 * d0 + d1 * d1) + d2 * d2;
 }
 
-/* First i in [0, m) whose running sum v[0] + ... + v[i] exceeds t; when
- * none does (rounding at the end of the range), the last i with v[i] > 0.
- * *before receives the running sum before i.  Returns -1 if every v is 0. */
-static int64_t kpp_search(const double *v, int64_t m, double t, double *before) {
-  double acc = 0.0;
-  for (int64_t i = 0; i < m; ++i) {
-    const double nx = acc + v[i];
-    if (nx > t) {
-      *before = acc;
-      return i;
+/* label_i = the j whose centre X[centres[j]] is nearest to x_i, the lowest j
+ * on ties (the hard assignment that turns the seeds into the first
+ * responsibility matrix). */
+int oracle_nearest(int64_t N, const double *X, int K, const int64_t *centres,
+                   int32_t *labels) {
+  if (N <= 0 || K <= 0 || !X || !centres || !labels) return OR_ERR_ARG;
+  for (int j = 0; j < K; ++j)
+    if (centres[j] < 0 || centres[j] >= N) return OR_ERR_ARG;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; ++i) {
+    double best = kpp_d2(X + 3 * i, X + 3 * centres[0]);
+    int32_t l = 0;
+    for (int j = 1; j < K; ++j) {
+      const double d = kpp_d2(X + 3 * i, X + 3 * centres[j]);
+      if (d < best) {
+        best = d;
+        l = j;
+      }
     }
-    acc = nx;
+    labels[i] = l;
   }
-  int64_t last = -1;
-  for (int64_t i = m - 1; i >= 0; --i)
-    if (v[i] > 0.0) {
-      last = i;
-      break;
-    }
-  acc = 0.0;
-  for (int64_t i = 0; i < last; ++i) acc += v[i];
-  *before = acc;
-  return last;
+  return OR_OK;
 }
 
 int oracle_kmeanspp(int64_t N, const double *X, int K, const double *u,
@@ -621,48 +615,30 @@ int oracle_kmeanspp(int64_t N, const double *X, int K, const double *u,
     if (!(u[j] >= 0.0 && u[j] < 1.0)) return OR_ERR_ARG;
   for (int64_t i = 0; i < 3 * N; ++i)
     if (!isfinite(X[i])) return OR_ERR_NONFINITE;
-  const int64_t nch = (N + KPP_CHUNK - 1) / KPP_CHUNK;
-  const int64_t ngr = (nch + KPP_GROUP - 1) / KPP_GROUP;
   double *D = malloc((size_t)N * sizeof(double));
-  double *T = malloc((size_t)nch * sizeof(double));
-  double *U = malloc((size_t)ngr * sizeof(double));
-  if (!D || !T || !U) {
-    free(D); free(T); free(U);
-    return OR_ERR_OOM;
-  }
+  if (!D) return OR_ERR_OOM;
   int64_t c0 = (int64_t)(u[0] * (double)N);
   if (c0 > N - 1) c0 = N - 1;
   centres[0] = c0;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i) D[i] = kpp_d2(X + 3 * i, X + 3 * c0);
   for (int j = 1; j < K; ++j) {
-    for (int64_t c = 0; c < nch; ++c) {
-      const int64_t lo = c * KPP_CHUNK, hi = lo + KPP_CHUNK < N ? lo + KPP_CHUNK : N;
-      double s = 0.0;
-      for (int64_t i = lo; i < hi; ++i) s += D[i];
-      T[c] = s;
-    }
-    for (int64_t g = 0; g < ngr; ++g) {
-      const int64_t lo = g * KPP_GROUP, hi = lo + KPP_GROUP < nch ? lo + KPP_GROUP : nch;
-      double s = 0.0;
-      for (int64_t c = lo; c < hi; ++c) s += T[c];
-      U[g] = s;
-    }
     double W = 0.0;
-    for (int64_t g = 0; g < ngr; ++g) W += U[g];
+    for (int64_t i = 0; i < N; ++i) W += D[i];
     int64_t pick = centres[j - 1];
     if (W > 0.0) {
       const double t = u[j] * W;
-      double b;
-      const int64_t g = kpp_search(U, ngr, t, &b);
-      const double t1 = t - b;
-      const int64_t clo = g * KPP_GROUP;
-      const int64_t cm = clo + KPP_GROUP < nch ? KPP_GROUP : nch - clo;
-      const int64_t c = clo + kpp_search(T + clo, cm, t1, &b);
-      const double t2 = t1 - b;
-      const int64_t ilo = c * KPP_CHUNK;
-      const int64_t im = ilo + KPP_CHUNK < N ? KPP_CHUNK : N - ilo;
-      pick = ilo + kpp_search(D + ilo, im, t2, &b);
+      double acc = 0.0;
+      int64_t i = 0;
+      for (; i < N; ++i) {
+        acc += D[i];
+        if (acc > t) break;
+      }
+      if (i == N) {                      /* rounding: no running sum above t */
+        i = N - 1;
+        while (!(D[i] > 0.0)) --i;
+      }
+      pick = i;
     }
     centres[j] = pick;
 #pragma omp parallel for schedule(static)
@@ -671,21 +647,78 @@ int oracle_kmeanspp(int64_t N, const double *X, int K, const double *u,
       if (d < D[i]) D[i] = d;
     }
   }
-  if (labels) {
+  if (labels) oracle_nearest(N, X, K, centres, labels);
+  free(D);
+  return OR_OK;
+}
+
+/* Replay of a given seeding, for checking another implementation's picks:
+ * along the centre sequence `centres` (its D2 after centres 0 .. j-1), for
+ * every step j >= 1 the pick of the flat running sum above (flat_pick[j];
+ * flat_pick[0] = floor(u[0] N)) and, in double-double arithmetic (Knuth's
+ * error-free TwoSum, relative error of order N 2^-106), the total W and the
+ * running sums before and at centres[j]: W2, before2 and at2 hold (hi, lo)
+ * pairs, K x 2 each (row 0 unused). */
+static void dd_add(double *hi, double *lo, double x) {
+  const double s = *hi + x;
+  const double bb = s - *hi;
+  const double e = (*hi - (s - bb)) + (x - bb);
+  const double l = *lo + e;
+  const double h = s + l;
+  *lo = l - (h - s);
+  *hi = h;
+}
+
+int oracle_kmeanspp_replay(int64_t N, const double *X, int K, const double *u,
+                           const int64_t *centres, int64_t *flat_pick,
+                           double *W2, double *before2, double *at2) {
+  if (N <= 0 || K <= 0 || K > N || !X || !u || !centres || !flat_pick || !W2 ||
+      !before2 || !at2)
+    return OR_ERR_ARG;
+  for (int j = 0; j < K; ++j)
+    if (centres[j] < 0 || centres[j] >= N || !(u[j] >= 0.0 && u[j] < 1.0))
+      return OR_ERR_ARG;
+  double *D = malloc((size_t)N * sizeof(double));
+  if (!D) return OR_ERR_OOM;
+  int64_t c0 = (int64_t)(u[0] * (double)N);
+  if (c0 > N - 1) c0 = N - 1;
+  flat_pick[0] = c0;
+  for (int q = 0; q < 2; ++q) W2[q] = before2[q] = at2[q] = 0.0;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; ++i) D[i] = kpp_d2(X + 3 * i, X + 3 * centres[0]);
+  for (int j = 1; j < K; ++j) {
+    const int64_t p = centres[j];
+    double W = 0.0, wh = 0.0, wl = 0.0, bh = 0.0, bl = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+      if (i == p) { bh = wh; bl = wl; }
+      W += D[i];
+      dd_add(&wh, &wl, D[i]);
+      if (i == p) { at2[2 * j] = wh; at2[2 * j + 1] = wl; }
+    }
+    W2[2 * j] = wh; W2[2 * j + 1] = wl;
+    before2[2 * j] = bh; before2[2 * j + 1] = bl;
+    int64_t pick = centres[j - 1];
+    if (W > 0.0) {
+      const double t = u[j] * W;
+      double acc = 0.0;
+      int64_t i = 0;
+      for (; i < N; ++i) {
+        acc += D[i];
+        if (acc > t) break;
+      }
+      if (i == N) {
+        i = N - 1;
+        while (!(D[i] > 0.0)) --i;
+      }
+      pick = i;
+    }
+    flat_pick[j] = pick;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
-      double best = kpp_d2(X + 3 * i, X + 3 * centres[0]);
-      int32_t l = 0;
-      for (int j = 1; j < K; ++j) {
-        const double d = kpp_d2(X + 3 * i, X + 3 * centres[j]);
-        if (d < best) {
-          best = d;
-          l = j;
-        }
-      }
-      labels[i] = l;
+      const double d = kpp_d2(X + 3 * i, X + 3 * p);
+      if (d < D[i]) D[i] = d;
     }
   }
-  free(D); free(T); free(U);
+  free(D);
   return OR_OK;
 }

@@ -8,6 +8,7 @@ import torch
 import oracle
 import paper_2307_00071_amd as gmm
 from paper_2307_00071_amd import synth
+from tests.parity import mixture_errors, rel as _rel
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -17,9 +18,9 @@ def _to(x, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(x)).to(DEV, dtype)
 
 
-def _rel(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) /
-                 max(np.linalg.norm(b), 1e-300))
+def _one_step_errors(r, X, ref):
+    got = (r.weights.cpu().numpy(), r.means.cpu().numpy(), r.covariances.cpu().numpy())
+    return mixture_errors(got, ref, X)
 
 
 def _frames(count, seed, nmin, nmax, kmin, kmax):
@@ -92,9 +93,8 @@ def test_batched_one_step_and_two_pass():
         torch.cuda.synchronize()
         for (X, k), th, r in zip(frames, thetas, res):
             wr, mur, covr, L0 = oracle.em_step(X, *(a.astype(np.float64) for a in th), 1e-3)
-            assert _rel(r.weights.cpu().numpy(), wr) <= 1e-5
-            assert _rel(r.means.cpu().numpy(), mur) <= 1e-5
-            assert _rel(r.covariances.cpu().numpy(), covr) <= 1e-5
+            e = _one_step_errors(r, X, (wr, mur, covr))
+            assert max(e.values()) <= 1e-5, (mode, k, e)
             assert abs(r.loglik[0].item() - L0) <= 1e-5 * max(abs(L0), X.shape[0])
 
 
@@ -165,9 +165,8 @@ def test_batched_culled_against_oracle(monkeypatch):
                           theta0_list=[tuple(_to(a) for a in th) for th in thetas])
     for (X, k), th, r in zip(frames, thetas, res):
         wr, mur, covr, L0 = oracle.em_step(X, *(a.astype(np.float64) for a in th), 1e-3)
-        assert _rel(r.weights.cpu().numpy(), wr) <= 1e-5
-        assert _rel(r.means.cpu().numpy(), mur) <= 1e-5
-        assert _rel(r.covariances.cpu().numpy(), covr) <= 1e-5
+        e = _one_step_errors(r, X, (wr, mur, covr))
+        assert max(e.values()) <= 1e-5, (k, e)
         assert abs(r.loglik[0].item() - L0) <= 1e-5 * max(abs(L0), X.shape[0])
 
 

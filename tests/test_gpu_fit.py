@@ -2,7 +2,9 @@
 
 Tolerances (relative, as the fit's acceptance bar states them):
   * one E+M step from identical float32 parameters: 1e-5 per parameter
-    array, ||A_gpu - A_ref||_F / ||A_ref||_F;
+    array, ||A_gpu - A_ref||_F / ||A_ref||_F, and 1e-5 per component with
+    pi_b >= 1e-3 (|dpi_b| / pi_b, |dmu_b| / (|mu_b| + RMS radius),
+    ||dSigma_b||_F / ||Sigma_b||_F; tests/parity.py);
   * log-likelihood after a fixed number of iterations: 1e-4, with the
     floor |dL| <= 1e-4 * max(|L|, N).
 """
@@ -13,14 +15,10 @@ import torch
 import oracle
 import paper_2307_00071_amd as gmm
 from paper_2307_00071_amd import _lib, synth
+from tests.parity import mixture_errors, rel as _rel
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) /
-                 max(np.linalg.norm(b), 1e-300))
 
 
 def _to(x, dtype=torch.float32):
@@ -85,8 +83,8 @@ def _one_step(X, K, theta, reg=1e-3, mode="shifted"):
     w, mu, cov, L = _fit(X, K, 1, reg=reg, theta0=th, mode=mode)
     wr, mur, covr, L0 = oracle.em_step(X, *th, reg)
     N = X.shape[0]
-    errs = dict(w=_rel(w, wr), mu=_rel(mu, mur), cov=_rel(cov, covr),
-                L0=abs(L[0] - L0) / max(abs(L0), N))
+    errs = mixture_errors((w, mu, cov), (wr, mur, covr), X)
+    errs["L0"] = abs(L[0] - L0) / max(abs(L0), N)
     return errs
 
 
@@ -462,3 +460,71 @@ def test_lidar_full_fit_properties(monkeypatch):
     cov = r2.covariances.cpu().numpy().astype(np.float64)
     ev = np.linalg.eigvalsh(0.5 * (cov + cov.transpose(0, 2, 1)))
     assert ev.min() >= 1e-3 * (1 - 1e-4), ev.min()
+
+
+# ----------------------------------------------- degenerate components (r3)
+
+def _compare_fit(X, K, T, labels=None, theta0=None, mode="shifted"):
+    th32 = None if theta0 is None else _theta32(*theta0)
+    w, mu, cov, L = _fit(X, K, T, labels=labels, theta0=th32, mode=mode)
+    wr, mur, covr, Lr = oracle.fit(X, K, 1e-3, T, labels=labels, theta0=th32)
+    errs = mixture_errors((w, mu, cov), (wr, mur, covr), X)
+    errs["L"] = float(np.abs(L - Lr).max() / max(np.abs(Lr).max(), X.shape[0]))
+    return (w, mu, cov), (wr, mur, covr), errs
+
+
+@pytest.mark.parametrize("mode", ["shifted", "two_pass"])
+def test_empty_component_from_an_unused_label(mode):
+    """A label value no point carries: N_b = eps, so mu_b = 0, Sigma_b =
+    lambda I and pi_b = eps / sum N; it stays empty (its weight underflows
+    for every point) through the following E+M steps, on both sides."""
+    _case("empty component (unused label) " + mode)
+    X = _blob_case(4) + np.float32(20.0)        # no point near the origin
+    K = 9
+    lab = synth.kmeanspp_labels(X, 8, 1)         # values 0..7: label 8 unused
+    for T in (0, 3):
+        got, ref, errs = _compare_fit(X, K, T, labels=lab, mode=mode)
+        print(T, errs)
+        assert max(errs.values()) <= 1e-5, (T, errs)
+        w, mu, cov = got
+        assert np.all(mu[8] == 0.0), mu[8]
+        np.testing.assert_array_equal(cov[8], np.float32(1e-3) * np.eye(3))
+        assert 0.0 < w[8] <= 1e-17 and abs(w[8] - ref[0][8]) <= 1e-5 * ref[0][8]
+
+
+@pytest.mark.parametrize("mode", ["shifted", "two_pass"])
+def test_component_far_from_every_point(mode):
+    """theta_0 holds a component 1 km from the cloud: every responsibility
+    of it is exactly zero, its statistics vanish, and the M-step gives the
+    empty-component result (mu = 0, Sigma = lambda I) as the oracle does;
+    the shifted update must not keep the old mean."""
+    _case("far component " + mode)
+    X = _blob_case(5)
+    lab = synth.kmeanspp_labels(X, 8, 2)
+    w, mu, cov = oracle.fit(X, 8, 1e-3, 2, labels=lab)[:3]
+    w = np.append(w * 0.95, 0.05)
+    mu = np.vstack([mu, [1000.0, -1000.0, 1000.0]])
+    cov = np.concatenate([cov, np.eye(3)[None]])
+    got, ref, errs = _compare_fit(X, 9, 1, theta0=(w, mu, cov), mode=mode)
+    print(errs)
+    assert max(errs.values()) <= 1e-5, errs
+    assert np.all(got[1][8] == 0.0), got[1][8]
+    np.testing.assert_array_equal(got[2][8], np.float32(1e-3) * np.eye(3))
+
+
+@pytest.mark.parametrize("mode", ["shifted", "two_pass"])
+def test_collapsed_component_of_identical_points(mode):
+    """600 copies of one point with a label of their own: the scatter is
+    exactly zero, Sigma_b = lambda I, mu_b = that point; the copies keep
+    responsibility one for it through the iterations."""
+    _case("collapsed component " + mode)
+    X = _blob_case(6, n_per=500)
+    p0 = np.array([[25.0, -3.5, 12.25]], np.float32)
+    X = np.ascontiguousarray(np.vstack([X, np.repeat(p0, 600, axis=0)]))
+    lab = np.concatenate([synth.kmeanspp_labels(X[:4000], 8, 3),
+                          np.full(600, 8)]).astype(np.int32)
+    got, ref, errs = _compare_fit(X, 9, 4, labels=lab, mode=mode)
+    print(errs)
+    assert max(errs.values()) <= 1e-5, errs
+    np.testing.assert_array_equal(got[1][8], p0[0])
+    np.testing.assert_allclose(got[2][8], 1e-3 * np.eye(3), rtol=0, atol=1e-9)

@@ -4,11 +4,14 @@ frame size (N = 307,200, K = 100) and the LiDAR size (N = 2,000,000,
 K = 1000).
 
 Reported per parameter array A in {pi, mu, Sigma}: ||A_gpu - A_ref||_F /
-||A_ref||_F; for log|Sigma_b|: the largest absolute difference over
+||A_ref||_F; per component with pi_b >= 1e-3 the largest |dpi_b| / pi_b,
+|dmu_b| / (|mu_b| + RMS radius) and ||dSigma_b||_F / ||Sigma_b||_F
+(tests/parity.py); for log|Sigma_b|: the largest absolute difference over
 components (nats); for L: |L_gpu - L_ref| / max(|L_ref|, N).
 
   * one E+M step from identical float32 parameters (both sides start from
-    the same theta): the bar is 1e-5 for pi, mu, Sigma and L;
+    the same theta): the bar is 1e-5 for pi, mu, Sigma, L and each
+    per-component error;
   * a full T-iteration fit from k-means++ labels: L(theta_T) to 1e-4, at
     the depth frame against the oracle run here, at the LiDAR scan (T = 50)
     against the oracle fit stored in tests/golden/lidar_fit_oracle.npz
@@ -25,6 +28,7 @@ import torch
 import oracle
 import paper_2307_00071_amd as gmm
 from paper_2307_00071_amd import synth
+from tests.parity import per_component
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -44,18 +48,24 @@ def _logdet(cov):
     return np.linalg.slogdet(np.asarray(cov, np.float64))[1]
 
 
-def _errors(got, ref, N):
+def _errors(got, ref, X):
     w, mu, cov, L = got
     wr, mur, covr, Lr = ref
-    return {"pi": _rel(w, wr), "mu": _rel(mu, mur), "Sigma": _rel(cov, covr),
-            "logdet": float(np.max(np.abs(_logdet(cov) - _logdet(covr)))),
-            "L": abs(L - Lr) / max(abs(Lr), N)}
+    e = {"pi": _rel(w, wr), "mu": _rel(mu, mur), "Sigma": _rel(cov, covr),
+         "logdet": float(np.max(np.abs(_logdet(cov) - _logdet(covr)))),
+         "L": abs(L - Lr) / max(abs(Lr), X.shape[0])}
+    e.update(per_component((w, mu, cov), (wr, mur, covr), X))
+    return e
+
+
+HEADER = ("| workload | moments | pi | mu | Sigma | log-det (nats) | L "
+          "| pi_b | mu_b | Sigma_b |\n|---|---|---|---|---|---|---|---|---|---|")
 
 
 def _report(title, mode, e):
-    print("| %s | %s | %.2e | %.2e | %.2e | %.2e | %.2e |" % (
-        title, mode, e["pi"], e["mu"], e["Sigma"], e["logdet"], e["L"]),
-        flush=True)
+    print("| %s | %s | %.2e | %.2e | %.2e | %.2e | %.2e | %.2e | %.2e | %.2e |" % (
+        title, mode, e["pi"], e["mu"], e["Sigma"], e["logdet"], e["L"],
+        e["pi_b"], e["mu_b"], e["cov_b"]), flush=True)
 
 
 def _gpu_fit(Xt, K, iters, mode, labels=None, theta0=None):
@@ -80,7 +90,7 @@ def _one_step_report(title, X, K, theta):
     out = {}
     for mode in MODES:
         w, mu, cov, L = _gpu_fit(Xt, K, 1, mode, theta0=th)
-        e = _errors((w, mu, cov, L[1]), (wr, mur, covr, Lr1), N)
+        e = _errors((w, mu, cov, L[1]), (wr, mur, covr, Lr1), X)
         _report(title + " one step", mode, e)
         out[mode] = e
     return out
@@ -93,19 +103,18 @@ def test_precision_depth_frame():
     lab = synth.kmeanspp_labels(X, K, 1)
     wr, mur, covr, Lr = oracle.fit(X, K, 1e-3, T, labels=lab)
     N = X.shape[0]
-    print("| workload | moments | pi | mu | Sigma | log-det (nats) | L |")
-    print("|---|---|---|---|---|---|---|")
+    print(HEADER)
     theta3 = oracle.fit(X, K, 1e-3, 3, labels=lab)[:3]
     one = _one_step_report("depth N=307200 K=100", X, K, theta3)
     Xt = _to(X)
     full = {}
     for mode in MODES:
         w, mu, cov, L = _gpu_fit(Xt, K, T, mode, labels=lab)
-        e = _errors((w, mu, cov, L[-1]), (wr, mur, covr, Lr[-1]), N)
+        e = _errors((w, mu, cov, L[-1]), (wr, mur, covr, Lr[-1]), X)
         _report("depth N=307200 K=100 T=100", mode, e)
         full[mode] = e
     for mode in MODES:
-        for key in ("pi", "mu", "Sigma", "L"):
+        for key in ("pi", "mu", "Sigma", "L", "pi_b", "mu_b", "cov_b"):
             assert one[mode][key] <= 1e-5, (mode, key, one[mode][key])
         assert full[mode]["L"] <= 1e-4, (mode, full[mode]["L"])
 
@@ -118,11 +127,10 @@ def test_precision_lidar_scan():
     rng = np.random.default_rng(5)
     sub = np.ascontiguousarray(X[np.sort(rng.choice(X.shape[0], 100000, replace=False))])
     theta = oracle.fit(sub, K, 1e-3, 3, labels=synth.kmeanspp_labels(sub, K, 1))[:3]
-    print("| workload | moments | pi | mu | Sigma | log-det (nats) | L |")
-    print("|---|---|---|---|---|---|---|")
+    print(HEADER)
     one = _one_step_report("lidar N=2000000 K=1000", X, K, theta)
     for mode in MODES:
-        for key in ("pi", "mu", "Sigma", "L"):
+        for key in ("pi", "mu", "Sigma", "L", "pi_b", "mu_b", "cov_b"):
             assert one[mode][key] <= 1e-5, (mode, key, one[mode][key])
 
 
@@ -136,12 +144,11 @@ def test_precision_lidar_full_fit():
     N = X.shape[0]
     _, lab = oracle.kmeanspp(X.astype(np.float64), K, np.random.default_rng(1).random(K))
     Xt = _to(X)
-    print("| workload | moments | pi | mu | Sigma | log-det (nats) | L |")
-    print("|---|---|---|---|---|---|---|")
+    print(HEADER)
     out = {}
     for mode in MODES:
         w, mu, cov, L = _gpu_fit(Xt, K, T, mode, labels=lab)
-        e = _errors((w, mu, cov, L[-1]), (ref["w"], ref["mu"], ref["cov"], ref["L"][-1]), N)
+        e = _errors((w, mu, cov, L[-1]), (ref["w"], ref["mu"], ref["cov"], ref["L"][-1]), X)
         _report("lidar N=2000000 K=1000 T=50", mode, e)
         hist = np.abs(L - ref["L"]) / np.maximum(np.abs(ref["L"]), N)
         out[mode] = (e, hist.max())
