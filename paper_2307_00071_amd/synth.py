@@ -15,6 +15,9 @@ Workloads (all float32, metres):
   6-12 random planar patches and oriented boxes at 0.5-8 m, with Gaussian
   range noise along each ray; every ray hits, so N = 307,200.  It stands
   in for the indoor RGB-D frames the paper evaluates on.
+* ``depth_intensity_frame`` - the same frame with a per-point intensity
+  (per-surface albedo, a smooth positional texture and noise): the 4D
+  (x, y, z, intensity) cloud of the paper's model.
 * ``batched_frames``  - 64 depth frames (seeds 1000+f) subsampled to
   N_f ~ U{20000..300000}, each with K_f ~ U{16..200}.
 * ``lidar_scan``      - a 64-ring spinning scan (elevation -25..+15 deg,
@@ -107,14 +110,9 @@ def _ray_vcyl(o, d, cxy, r, z0, z1):
     return np.where(ok, t, np.inf)
 
 
-def depth_frame(seed: int = 0, width: int = 640, height: int = 480,
-                fx: float = 525.0, fy: float = 525.0, cx: float = 319.5,
-                cy: float = 239.5, sigma: float = 0.01,
-                noise_seed=None) -> np.ndarray:
-    """One synthetic depth frame in the camera frame (x right, y down,
-    z forward).  Returns float32 (width*height, 3); every ray hits.
-    ``noise_seed`` (optional) draws the range noise from its own generator:
-    a second noisy render of the same scene."""
+def _depth_render(seed, width, height, fx, fy, cx, cy, sigma, noise_seed):
+    """Ray casting of one synthetic scene: (points float64 (N, 3), id of the
+    surface each ray hit: 0..5 the room's faces, 6 + j object j)."""
     rng = np.random.default_rng(seed)
     u, v = np.meshgrid(np.arange(width, dtype=np.float64),
                        np.arange(height, dtype=np.float64))
@@ -129,8 +127,10 @@ def depth_frame(seed: int = 0, width: int = 640, height: int = 480,
     with np.errstate(divide="ignore", invalid="ignore"):
         tw = np.where(d > 0, hi / d, np.where(d < 0, lo / d, np.inf))
     t = tw.min(axis=1)
+    face = tw.argmin(axis=1) * 2 + (d[np.arange(d.shape[0]), tw.argmin(axis=1)] > 0)
+    hit = face.astype(np.int64)
     n_obj = int(rng.integers(6, 13))
-    for _ in range(n_obj):
+    for j in range(n_obj):
         # place the object centre along a random in-frustum ray at 0.5-8 m
         px, py = rng.uniform(0, width), rng.uniform(0, height)
         ray = np.array([(px - cx) / fx, (py - cy) / fy, 1.0])
@@ -144,11 +144,43 @@ def depth_frame(seed: int = 0, width: int = 640, height: int = 480,
         else:
             th = _ray_rect(o, d, center, R[:, 2], R[:, 0], R[:, 1],
                            rng.uniform(0.2, 1.2), rng.uniform(0.2, 1.2))
+        hit = np.where(th < t, 6 + j, hit)
         t = np.minimum(t, th)
     assert np.all(np.isfinite(t))
     nrng = rng if noise_seed is None else np.random.default_rng(noise_seed)
     t = t + sigma * nrng.standard_normal(t.shape)
-    return (t[:, None] * d).astype(np.float32)
+    return t[:, None] * d, hit
+
+
+def depth_frame(seed: int = 0, width: int = 640, height: int = 480,
+                fx: float = 525.0, fy: float = 525.0, cx: float = 319.5,
+                cy: float = 239.5, sigma: float = 0.01,
+                noise_seed=None) -> np.ndarray:
+    """One synthetic depth frame in the camera frame (x right, y down,
+    z forward).  Returns float32 (width*height, 3); every ray hits.
+    ``noise_seed`` (optional) draws the range noise from its own generator:
+    a second noisy render of the same scene."""
+    pts, _ = _depth_render(seed, width, height, fx, fy, cx, cy, sigma, noise_seed)
+    return pts.astype(np.float32)
+
+
+def depth_intensity_frame(seed: int = 0, width: int = 640, height: int = 480,
+                          sigma_i: float = 0.02) -> np.ndarray:
+    """The depth frame of ``depth_frame(seed)`` with an intensity channel:
+    float32 (N, 4) = (x, y, z, intensity).  Each surface has its own albedo
+    U[0.15, 0.85], modulated by a smooth texture 0.1 sin(2.3 x) cos(1.7 y)
+    + 0.05 sin(3.1 z) of the position and N(0, sigma_i^2) noise (the
+    points are exactly those of depth_frame(seed); the intensities come
+    from generators of their own).  It stands in for the depth-intensity
+    image pairs the paper models."""
+    pts, hit = _depth_render(seed, width, height, 525.0, 525.0, 319.5, 239.5,
+                             0.01, None)
+    rng = np.random.default_rng(seed + 7919)
+    albedo = rng.uniform(0.15, 0.85, int(hit.max()) + 1)
+    tex = (0.1 * np.sin(2.3 * pts[:, 0]) * np.cos(1.7 * pts[:, 1])
+           + 0.05 * np.sin(3.1 * pts[:, 2]))
+    inten = albedo[hit] + tex + sigma_i * rng.standard_normal(pts.shape[0])
+    return np.concatenate([pts, inten[:, None]], axis=1).astype(np.float32)
 
 
 def batched_frames(seed_base: int = 1000, count: int = 64, nmin: int = 20000,
