@@ -124,6 +124,32 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
                    double *loglik, const gmm_fit_opts *opts, void *ws,
                    size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------ allocation-free fitting
+ * gmm_fit_noalloc: gmm_fit for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * results and errors as gmm_fit with ws = NULL, except:
+ *  - no workspace argument: the workspace lives in one static device array
+ *    of GMM_FIT_NOALLOC_MAX_BYTES per GPU, part of the library's code object
+ *    (held by every GPU the library runs on until the process ends).  A fit
+ *    whose gmm_fit_workspace_size() exceeds it returns GMM_ERR_UNSUPPORTED
+ *    before anything is enqueued.
+ *  - nothing is allocated: no hipMalloc / hipMallocAsync / hipFree, no
+ *    graph capture, no autotuning, no profiling events; the kernels are
+ *    launched directly on `stream`, and every value a fit needs zeroed is
+ *    cleared by its own kernels at the start of the call.
+ *  - always synchronises `stream` once at the end (GMM_FLAG_ASYNC is
+ *    GMM_ERR_INVALID_ARG): the status word lives in the shared array, so
+ *    the call cannot be recorded into a stream capture.
+ *  - every call on one GPU shares that GPU's array: calls that overlap on
+ *    one GPU (other host threads, other streams) race and give undefined
+ *    results; serialise them. */
+#define GMM_FIT_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+
+gmm_status gmm_fit_noalloc(const float *pts, int64_t n, int32_t k,
+                           const int32_t *init_labels, float *w, float *mu,
+                           float *cov, double *loglik, const gmm_fit_opts *opts,
+                           void *stream);
+
 /* --------------------------------------------------------- log-likelihood
  * gmm_loglik: L = sum_n ln sum_b pi_b N(y_n | mu_b, Sigma_b) with
  * y_n = R(omega) x_n + t (eq. 2-3 applied to the transformed cloud).

@@ -13,7 +13,7 @@ import ctypes
 
 from . import _lib
 
-__all__ = ["fit", "fit_batched", "loglik", "loglik_backward", "GMMLogLik",
+__all__ = ["fit", "fit_noalloc", "fit_batched", "loglik", "loglik_backward", "GMMLogLik",
            "FitResult", "kmeanspp"]
 
 
@@ -101,6 +101,42 @@ def fit(points, k, iters=100, reg_covar=1e-3, labels=None, theta0=None,
                      _ptr(L), ctypes.byref(opts), _ptr(ws), ws.numel(),
                      _stream(dev))
     _lib.check(st)
+    return FitResult(w, mu, cov, L)
+
+
+def fit_noalloc(points, k, iters=100, reg_covar=1e-3, labels=None, theta0=None,
+                moment_mode="shifted"):
+    """``fit`` through gmm_fit_noalloc: the library allocates no device
+    memory (its workspace is a fixed per-GPU array of
+    GMM_FIT_NOALLOC_MAX_BYTES); the caller's tensors are the only buffers.
+    Overlapping calls on one GPU race."""
+    torch = _torch()
+    lib = _lib.load()
+    pts = _check_points(points)
+    dev = pts.device
+    n = pts.shape[0]
+    opts = _lib.FitOpts(int(iters), float(reg_covar),
+                        {"shifted": _lib.GMM_MOMENTS_SHIFTED,
+                         "two_pass": _lib.GMM_MOMENTS_TWO_PASS}[moment_mode], 0)
+    if labels is not None:
+        lab = labels.to(device=dev, dtype=torch.int32).contiguous()
+        if lab.shape != (n,):
+            raise ValueError("labels must have shape (N,)")
+        w = torch.empty(k, dtype=torch.float32, device=dev)
+        mu = torch.empty(k, 3, dtype=torch.float32, device=dev)
+        cov = torch.empty(k, 3, 3, dtype=torch.float32, device=dev)
+    elif theta0 is not None:
+        lab = None
+        w, mu, cov = (a.to(device=dev, dtype=torch.float32).contiguous().clone()
+                      for a in theta0)
+        if w.shape != (k,) or mu.shape != (k, 3) or cov.shape != (k, 3, 3):
+            raise ValueError("theta0 shapes must be (K,), (K,3), (K,3,3)")
+    else:
+        raise ValueError("give labels or theta0")
+    L = torch.empty(iters + 1, dtype=torch.float64, device=dev)
+    _lib.check(lib.gmm_fit_noalloc(_ptr(pts), n, k, _ptr(lab), _ptr(w), _ptr(mu),
+                                   _ptr(cov), _ptr(L), ctypes.byref(opts),
+                                   _stream(dev)))
     return FitResult(w, mu, cov, L)
 
 

@@ -17,10 +17,11 @@ GMM_MOMENTS_SHIFTED = 0
 GMM_MOMENTS_TWO_PASS = 1
 GMM_FLAG_ASYNC = 1
 GMM_MAX_K = 1024
+GMM_FIT_NOALLOC_MAX_BYTES = 64 << 20
 
 EXPORTS = (
     "gmm_status_string", "gmm_last_error", "gmm_workspace_status",
-    "gmm_fit_workspace_size", "gmm_fit",
+    "gmm_fit_workspace_size", "gmm_fit", "gmm_fit_noalloc",
     "gmm_loglik_workspace_size", "gmm_loglik",
     "gmm_loglik_backward_workspace_size", "gmm_loglik_backward",
     "gmm_fit_batched_workspace_size", "gmm_fit_batched",
@@ -66,6 +67,9 @@ def load():
     lib.gmm_fit.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp,
                             ctypes.POINTER(FitOpts), vp, sz, vp]
     lib.gmm_fit.restype = ctypes.c_int
+    lib.gmm_fit_noalloc.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp,
+                                    ctypes.POINTER(FitOpts), vp]
+    lib.gmm_fit_noalloc.restype = ctypes.c_int
     lib.gmm_loglik_workspace_size.argtypes = [i64, i32]
     lib.gmm_loglik_workspace_size.restype = sz
     lib.gmm_loglik.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]

@@ -889,6 +889,30 @@ gmm_status enqueue_fit(Run &r, const float *pts, int64_t n,
                   loglik ? loglik + opts->iters : nullptr, nullptr, w, mu, cov);
 }
 
+// Argument checks, launch configuration and workspace layout of a fit.
+gmm_status fit_setup(const float *pts, int64_t n, int32_t k, const float *w,
+                     const float *mu, const float *cov, const gmm_fit_opts *opts,
+                     void *stream, Run *r) {
+  gmm_status st = check_sizes(n, k, true);
+  if (st != GMM_OK) return st;
+  if (!pts || !w || !mu || !cov || !opts)
+    return fail(GMM_ERR_INVALID_ARG, "NULL pointer argument");
+  if (opts->iters < 0) return fail(GMM_ERR_INVALID_ARG, "iters < 0");
+  if (!(opts->reg_covar >= 0.0) || !isfinite(opts->reg_covar))
+    return fail(GMM_ERR_INVALID_ARG, "reg_covar must be finite and >= 0");
+  if (opts->moment_mode != GMM_MOMENTS_SHIFTED &&
+      opts->moment_mode != GMM_MOMENTS_TWO_PASS)
+    return fail(GMM_ERR_INVALID_ARG, "unknown moment_mode");
+  if (opts->flags & ~GMM_FLAG_ASYNC) return fail(GMM_ERR_INVALID_ARG, "unknown flags");
+  r->K = k;
+  if (!pick_cfg(k, n, &r->c)) return fail(GMM_ERR_UNSUPPORTED, "no launch configuration for k=%d", k);
+  r->cull = pick_cull_cfg(k, n, &r->cc);
+  if (r->cull) debug_cfg("fit", k, n, r->cc.name, r->cc.grid, r->cc.block, r->cc.lds);
+  r->L = ws_layout(n, k, r->c, 0, 0, true);
+  r->s = static_cast<hipStream_t>(stream);
+  return GMM_OK;
+}
+
 // ------------------------------------------------------------ graph cache
 // A fit repeated with identical arguments (same buffers, sizes, options and
 // workspace) is captured once into a hipGraph on a private stream and then
@@ -1382,6 +1406,38 @@ gmm_status enqueue_batched(BatchRun &r, const int32_t *labels, float *w,
 
 }  // namespace
 
+// ------------------------------------------------------ allocation-free fit
+// Device memory of gmm_fit_noalloc: one array per GPU, in the code object,
+// held until the process ends.  Host code never passes the symbol itself to
+// a kernel (on the host it names a stand-in, not device memory): the device
+// address is read once per device with hipGetSymbolAddress and kept.
+static __device__ __align__(256) unsigned char scratch[GMM_FIT_NOALLOC_MAX_BYTES];
+
+namespace {
+
+static_assert(GMM_FIT_NOALLOC_MAX_BYTES % 256 == 0, "scratch size");
+constexpr size_t kScratchBytes = GMM_FIT_NOALLOC_MAX_BYTES;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[64];
+
+gmm_status scratch_address(void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(GMM_ERR_DEVICE, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || (reinterpret_cast<uintptr_t>(p) & 255))
+      return fail(GMM_ERR_DEVICE, "scratch array address %p unusable", p);
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return GMM_OK;
+}
+
+}  // namespace
+
 // ===================================================================== C ABI
 
 extern "C" {
@@ -1424,24 +1480,9 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
                    double *loglik, const gmm_fit_opts *opts, void *ws,
                    size_t ws_bytes, void *stream) {
   g_err[0] = 0;
-  gmm_status st = check_sizes(n, k, true);
-  if (st != GMM_OK) return st;
-  if (!pts || !w || !mu || !cov || !opts)
-    return fail(GMM_ERR_INVALID_ARG, "NULL pointer argument");
-  if (opts->iters < 0) return fail(GMM_ERR_INVALID_ARG, "iters < 0");
-  if (!(opts->reg_covar >= 0.0) || !isfinite(opts->reg_covar))
-    return fail(GMM_ERR_INVALID_ARG, "reg_covar must be finite and >= 0");
-  if (opts->moment_mode != GMM_MOMENTS_SHIFTED &&
-      opts->moment_mode != GMM_MOMENTS_TWO_PASS)
-    return fail(GMM_ERR_INVALID_ARG, "unknown moment_mode");
-  if (opts->flags & ~GMM_FLAG_ASYNC) return fail(GMM_ERR_INVALID_ARG, "unknown flags");
   Run r;
-  r.K = k;
-  if (!pick_cfg(k, n, &r.c)) return fail(GMM_ERR_UNSUPPORTED, "no launch configuration for k=%d", k);
-  r.cull = pick_cull_cfg(k, n, &r.cc);
-  if (r.cull) debug_cfg("fit", k, n, r.cc.name, r.cc.grid, r.cc.block, r.cc.lds);
-  r.L = ws_layout(n, k, r.c, 0, 0, true);
-  r.s = static_cast<hipStream_t>(stream);
+  gmm_status st = fit_setup(pts, n, k, w, mu, cov, opts, stream, &r);
+  if (st != GMM_OK) return st;
   WsGuard guard;
   if ((st = get_ws(&ws, &ws_bytes, r.L.total, r.s, &guard)) != GMM_OK) return st;
   r.ws = ws;
@@ -1483,6 +1524,29 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
   r.sink = g_prof.reps > 0 ? &g_prof.pending : nullptr;
   if ((st = enqueue_fit(r, pts, n, init_labels, w, mu, cov, loglik, opts, true)) != GMM_OK) return st;
   return finish(r, sync);
+}
+
+gmm_status gmm_fit_noalloc(const float *pts, int64_t n, int32_t k,
+                           const int32_t *init_labels, float *w, float *mu,
+                           float *cov, double *loglik, const gmm_fit_opts *opts,
+                           void *stream) {
+  g_err[0] = 0;
+  Run r;
+  gmm_status st = fit_setup(pts, n, k, w, mu, cov, opts, stream, &r);
+  if (st != GMM_OK) return st;
+  if (opts->flags & GMM_FLAG_ASYNC)
+    return fail(GMM_ERR_INVALID_ARG, "gmm_fit_noalloc always synchronises (no GMM_FLAG_ASYNC)");
+  if (r.L.total > kScratchBytes)
+    return fail(GMM_ERR_UNSUPPORTED,
+                "a fit of n=%lld k=%d needs %zu bytes of scratch; the allocation-free fit holds %zu",
+                (long long)n, k, r.L.total, kScratchBytes);
+  if ((st = scratch_address(&r.ws)) != GMM_OK) return st;
+  // direct launches only: no graph capture, no autotuning and no profiling
+  // events, each of which allocates
+  r.sink = nullptr;
+  if ((st = enqueue_fit(r, pts, n, init_labels, w, mu, cov, loglik, opts, false)) != GMM_OK)
+    return st;
+  return finish(r, true);
 }
 
 size_t gmm_loglik_workspace_size(int64_t n, int32_t k) {
