@@ -29,7 +29,16 @@ Prints one JSON line:
   kinit           k-means++ seeding on the GPU (gmm_kmeanspp) at the depth
                   frame (K = 100) and the LiDAR scan (K = 1000), beside the
                   oracle's seeding of the same draws on the host cores
+  blobs           the small fit: N = 10,000 points from 8 anisotropic
+                  Gaussians, K = 8, T = 50, GPU k-means++ seeding:
+                  microseconds per EM iteration (launch-latency bound)
+  registration    log-likelihood of a moved cloud (N = 100,000) under a
+                  fitted K = 200 mixture, its forward and backward kernels
+                  and the gradient with respect to pose, points and
+                  mixture; roofline of the backward tile kernel; the
+                  oracle's likelihood + gradient on the host beside it
   cpu_baseline    the FP64 CPU oracle on a bounded sample of the same fit
+                  (all host cores); cpu_baseline_1thread the same on one
 """
 from __future__ import annotations
 
@@ -46,6 +55,8 @@ if ROOT not in sys.path:
 METRIC = ("EM iters/s and point-component evals/s at N=307200,K=100; "
           "batched vs plain")
 FLOP_PER_EVAL = 42          # distance 19 + log-sum-exp 3 + statistics 20
+FLOP_PER_EVAL_FWD = 22      # registration forward: distance 19 + log-sum-exp 3
+FLOP_PER_EVAL_BWD = 57      # backward: forward 22 + gradient terms 15 + statistics 20
 PEAK_FP32_VECTOR = 157.3    # TFLOP/s, MI355X FP32 vector (packed FMA rate)
 PEAK_FP32_NONPACKED = 78.6  # TFLOP/s, one FP32 FMA per lane per cycle
 PROFILE_REPS = 16           # tile launches per timed event pair
@@ -76,6 +87,8 @@ def parse():
     ap.add_argument("--batched-iters", type=int, default=20)
     ap.add_argument("--no-lidar", action="store_true")
     ap.add_argument("--no-kinit", action="store_true")
+    ap.add_argument("--no-blobs", action="store_true")
+    ap.add_argument("--no-registration", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device tensor copy "
                          "(a known-size reference for memory counters)")
@@ -98,19 +111,26 @@ def tile_traffic_bytes(N, K):
                      t["write_kib"] * t["write_factor"])
 
 
-def cpu_baseline(X, lab, K, T_hint, target_s):
+def cpu_baseline(X, lab, K, T_hint, target_s, threads=None):
     """Time the FP64 oracle (as it stands) on a bounded number of EM
     iterations of the same fit; report evals/s."""
     import oracle
+    prev = oracle.get_threads()
+    if threads:
+        oracle.set_threads(threads)
     threads = oracle.get_threads()
     N = X.shape[0]
     t0 = time.perf_counter()
     oracle.fit(X, K, 1e-3, 1, labels=lab)
     t1 = time.perf_counter() - t0
     iters = int(max(1, min(T_hint, round(target_s / max(t1, 1e-3)))))
-    t0 = time.perf_counter()
-    oracle.fit(X, K, 1e-3, iters, labels=lab)
-    dt = time.perf_counter() - t0
+    if iters == 1:
+        dt = t1
+    else:
+        t0 = time.perf_counter()
+        oracle.fit(X, K, 1e-3, iters, labels=lab)
+        dt = time.perf_counter() - t0
+    oracle.set_threads(prev)
     return {"value": N * K * iters / dt, "unit": "point-component evals/s",
             "cores": threads, "kind": "oracle",
             "sample": "%d EM iterations (label M-step + %d x (E-step + "
@@ -118,22 +138,24 @@ def cpu_baseline(X, lab, K, T_hint, target_s):
                       "K=%d fit, FP64, %.1f s wall" % (iters, iters, N, K, dt)}
 
 
-def batched_vs_plain(T, reps=2):
-    """64 uneven frames: one gmm_fit_batched call vs 64 gmm_fit calls."""
+def batched_vs_plain(T, reps=2, single_evals_per_s=None):
+    """64 uneven frames: one gmm_fit_batched call (soft-pass shape chosen by
+    the library's autotuner on the first call) vs 64 gmm_fit calls."""
     import numpy as np
     import torch
 
     import paper_2307_00071_amd as gmm
-    from paper_2307_00071_amd import synth
+    from paper_2307_00071_amd import _lib, synth
 
     dev = torch.device("cuda:0")
     frames = synth.batched_frames()
     pts = [torch.from_numpy(X).to(dev) for X, _ in frames]
     ks = [k for _, k in frames]
+    ns = [X.shape[0] for X, _ in frames]
     labs = [torch.from_numpy(synth.kmeanspp_labels(X, k, 1)).to(dev)
             for X, k in frames]
     evals = sum(X.shape[0] * k for X, k in frames) * T
-    ws = torch.empty(gmm.fit_batched_workspace_bytes([p.shape[0] for p in pts], ks, T),
+    ws = torch.empty(gmm.fit_batched_workspace_bytes(ns, ks, T),
                      dtype=torch.uint8, device=dev)
 
     def batched():
@@ -143,23 +165,47 @@ def batched_vs_plain(T, reps=2):
         return [gmm.fit(p, k, iters=T, labels=l) for p, k, l in zip(pts, ks, labs)]
 
     out = {}
-    for name, fn in (("batched", batched), ("plain", plain)):
-        fn()
+    _lib.set_autotune(True)
+    try:
+        batched()                      # tunes the soft-pass shape
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            res = fn()
+        out["shape"] = _lib.batch_config(ns, ks)
+        for name, fn in (("batched", batched), ("plain", plain)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                res = fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            out[name + "_ms"] = 1e3 * dt
+            out[name + "_evals_per_s"] = evals / dt
+            out[name + "_final_loglik_sum"] = float(sum(r.loglik[-1].item() for r in res))
+        # soft-pass kernel time of the batched fit (direct launches)
+        _lib.profile_read()
+        _lib.profile_pairs()
+        _lib.profile_enable(PROFILE_REPS)
+        batched()
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        out[name + "_ms"] = 1e3 * dt
-        out[name + "_evals_per_s"] = evals / dt
-        out[name + "_final_loglik_sum"] = float(sum(r.loglik[-1].item() for r in res))
+        _lib.profile_enable(0)
+        ms, n = _lib.profile_read()
+        _lib.profile_pairs()
+    finally:
+        _lib.set_autotune(False)
+    avg = ms / max(n, 1) * 1e-3
+    ach = FLOP_PER_EVAL * (evals / T) / avg / 1e12
+    out["roofline"] = {"bound": "alu", "kernel": "batched soft pass, shape %s" % out["shape"],
+                       "achieved": ach, "peak": PEAK_FP32_VECTOR, "unit": "TFLOP/s",
+                       "frac": ach / PEAK_FP32_VECTOR, "avg_launch_us": 1e6 * avg,
+                       "launches": n}
     out.update({"frames": len(frames), "iters": T,
                 "point_component_evals": evals,
                 "speedup": out["plain_ms"] / out["batched_ms"],
                 "workload": "64 synthetic depth frames subsampled to "
                             "N_f~U[20000,300000], K_f~U[16,200], k-means++ "
                             "labels, lambda=1e-3"})
+    if single_evals_per_s:
+        out["batched_vs_single_frame_evals_rate"] = out["batched_evals_per_s"] / single_evals_per_s
     return out
 
 
@@ -245,6 +291,151 @@ def kinit_bench(reps=3, cpu=True):
             r["identical_to_oracle"] = bool((cen.cpu().numpy() == rc).all() and
                                             (lab.cpu().numpy() == rl).all())
         out[name] = r
+    return out
+
+
+def blobs_fit(reps=10):
+    """The small fit: N = 10,000 points from 8 anisotropic Gaussians (1250
+    each), K = 8, T = 50, lambda = 1e-3, seeded by the GPU k-means++ (draws
+    from seed 1).  Fits replayed as captured graphs; median of reps."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2307_00071_amd as gmm
+    from paper_2307_00071_amd import synth
+
+    dev = torch.device("cuda:0")
+    X, _, _ = synth.gaussian_blobs(0)
+    N, K, T = X.shape[0], 8, 50
+    pts = torch.from_numpy(X).to(dev)
+    lab, _ = gmm.kmeanspp(pts, K, seed=1)
+    ws = torch.empty(gmm.fit_workspace_bytes(N, K, T), dtype=torch.uint8, device=dev)
+
+    def fit():
+        return gmm.fit(pts, K, iters=T, reg_covar=1e-3, labels=lab, workspace=ws)
+
+    for _ in range(3):
+        fit()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = fit()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    labn = lab.cpu().numpy()
+    t0 = time.perf_counter()
+    Lo = oracle.fit(X, K, 1e-3, T, labels=labn)[3]
+    dto = time.perf_counter() - t0
+    L = r.loglik.cpu().numpy()
+    return {"workload": "N=10000 points from 8 anisotropic Gaussians (means "
+                        "U[0,10]^3 m, s~U[0.05,0.5] m), K=8, T=50, lambda=1e-3, "
+                        "GPU k-means++ labels (seed 1)",
+            "N": N, "K": K, "iters": T, "ms_per_fit": 1e3 * dt,
+            "us_per_iteration": 1e6 * dt / T, "em_iters_per_s": T / dt,
+            "final_loglik": float(L[-1]),
+            "final_loglik_rel_err_vs_oracle": abs(L[-1] - Lo[-1]) / max(abs(Lo[-1]), N),
+            "cpu_baseline": {"ms_per_fit": 1e3 * dto, "us_per_iteration": 1e6 * dto / T,
+                             "cores": oracle.get_threads(), "kind": "oracle",
+                             "sample": "the whole 50-iteration fit from the same labels"}}
+
+
+def registration(reps=20, cpu=True):
+    """Registration likelihood and gradient: a K = 200 mixture fitted (GPU,
+    20 iterations from k-means++ labels) to the depth frame, a source of
+    N = 100,000 points from a second noisy render of the scene under a
+    random pose (|omega| <= 0.3 rad, |t| <= 0.5 m)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2307_00071_amd as gmm
+    from paper_2307_00071_amd import _lib, synth
+
+    dev = torch.device("cuda:0")
+    K, Nsrc = 200, 100_000
+    Xt = torch.from_numpy(synth.depth_frame(0)).to(dev)
+    lab, _ = gmm.kmeanspp(Xt, K, seed=1)
+    th = gmm.fit(Xt, K, iters=20, reg_covar=1e-3, labels=lab)
+    w, mu, cov = th.weights, th.means, th.covariances
+    Y = synth.depth_frame(0, noise_seed=7)
+    rng = np.random.default_rng(101)
+    src = np.ascontiguousarray(Y[np.sort(rng.choice(Y.shape[0], Nsrc, replace=False))])
+    pose = torch.from_numpy(synth.random_pose(2).astype(np.float32)).to(dev)
+    pts = torch.from_numpy(src).to(dev)
+
+    def fwd():
+        return gmm.loglik(pts, w, mu, cov, pose6=pose, check=False)
+
+    def bwd():
+        return gmm.loglik_backward(pts, w, mu, cov, pose6=pose, check=False)
+
+    def both():
+        p = pose.clone().requires_grad_(True)
+        x = pts.clone().requires_grad_(True)
+        tw, tm, tc = (a.clone().requires_grad_(True) for a in (w, mu, cov))
+        L = gmm.GMMLogLik.apply(x, p, tw, tm, tc)
+        L.backward()
+        return L
+
+    out = {"workload": "K=200 mixture fitted to the 640x480 depth frame; "
+                       "N=100000 source points from a second noisy render "
+                       "under a random SE(3) pose (|omega|<=0.3 rad, "
+                       "|t|<=0.5 m); gradient w.r.t. pose, points, weights, "
+                       "means, covariances",
+           "N": Nsrc, "K": K}
+    for name, fn in (("forward", fwd), ("backward", bwd), ("forward_backward_autograd", both)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        out[name + "_ms"] = 1e3 * float(np.median(times))
+    out["evals_per_s"] = Nsrc * K / (out["forward_backward_autograd_ms"] * 1e-3)
+    # kernel times: each timed pair covers PROFILE_REPS back-to-back launches
+    kern = {}
+    for name, fn, flop in (("forward", fwd, FLOP_PER_EVAL_FWD),
+                           ("backward", bwd, FLOP_PER_EVAL_BWD)):
+        _lib.profile_read()
+        _lib.profile_pairs()
+        _lib.profile_enable(PROFILE_REPS)
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        _lib.profile_enable(0)
+        ms, n = _lib.profile_read()
+        pe, pa = _lib.profile_pairs()
+        avg = ms / max(n, 1) * 1e-3
+        ach = flop * Nsrc * K / avg / 1e12
+        kern[name] = {"avg_launch_us": 1e6 * avg, "launches": n,
+                      "achieved": ach, "frac": ach / PEAK_FP32_VECTOR,
+                      "evaluated_pair_fraction": pe / max(pa, 1),
+                      "flop_per_eval": flop}
+    out["kernels"] = kern
+    out["roofline"] = {"bound": "alu", "kernel": "em_bwd_kernel (dense)",
+                       "achieved": kern["backward"]["achieved"],
+                       "peak": PEAK_FP32_VECTOR, "unit": "TFLOP/s",
+                       "frac": kern["backward"]["frac"], "traffic": None}
+    if cpu:
+        th64 = tuple(a.cpu().numpy().astype(np.float64) for a in (w, mu, cov))
+        p64 = pose.cpu().numpy().astype(np.float64)
+        oracle.loglik_pose(src, p64, *th64)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            oracle.loglik_pose(src, p64, *th64)
+            oracle.loglik_grad(src, p64, *th64)
+        dto = (time.perf_counter() - t0) / 3
+        out["cpu_baseline"] = {"value": Nsrc * K / dto, "unit": "point-component evals/s",
+                               "ms": 1e3 * dto, "cores": oracle.get_threads(),
+                               "kind": "oracle",
+                               "sample": "likelihood + analytic gradient of the same "
+                                         "problem, FP64, mean of 3"}
     return out
 
 
@@ -340,17 +531,26 @@ def main():
                      # share of the N*K point-component pairs the kernel
                      # computed (the rest were shown to be exactly zero)
                      "evaluated_pair_fraction": pairs_eval / max(pairs_all, 1),
+                     # the same time against the FLOPs of the pairs the
+                     # kernel actually evaluated (dense-equivalent above)
                      "achieved_on_evaluated_pairs":
-                         achieved * pairs_eval / max(pairs_all, 1)},
+                         achieved * pairs_eval / max(pairs_all, 1),
+                     "frac_on_evaluated_pairs":
+                         achieved * pairs_eval / max(pairs_all, 1) / PEAK_FP32_VECTOR},
     }
     if not args.no_batched:
-        out["batched"] = batched_vs_plain(args.batched_iters)
+        out["batched"] = batched_vs_plain(args.batched_iters, single_evals_per_s=value)
     if not args.no_lidar:
         out["lidar"] = lidar_fit()
     if not args.no_kinit:
         out["kinit"] = kinit_bench(cpu=not args.no_cpu_baseline)
+    if not args.no_blobs:
+        out["blobs"] = blobs_fit()
+    if not args.no_registration:
+        out["registration"] = registration(cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, lab, K, T, args.cpu_seconds)
+        out["cpu_baseline_1thread"] = cpu_baseline(X, lab, K, T, 4.0, threads=1)
     print(json.dumps(out), flush=True)
 
 

@@ -66,7 +66,11 @@ typedef enum {
 enum { GMM_MOMENTS_SHIFTED = 0, GMM_MOMENTS_TWO_PASS = 1 };
 
 /* flags */
-#define GMM_FLAG_ASYNC 1u   /* do not synchronise; read the status later  */
+#define GMM_FLAG_ASYNC 1u          /* do not synchronise; read the status later */
+#define GMM_FLAG_DETERMINISTIC 2u  /* bitwise reproducible results: every
+                                      reduction here has a fixed order, so
+                                      this holds for every call (accepted,
+                                      changes nothing)                      */
 
 typedef struct {
     int32_t iters;        /* T >= 0 EM iterations (E-step + M-step each)   */
@@ -74,6 +78,14 @@ typedef struct {
                              after each M-step                             */
     int32_t moment_mode;  /* GMM_MOMENTS_*                                 */
     uint32_t flags;       /* GMM_FLAG_*                                    */
+    double tol;           /* >= 0; 0: exactly T iterations (the paper gives
+                             no stopping rule).  > 0 (gmm_fit only): after
+                             the M-step of iteration t, once
+                             |L(theta_t) - L(theta_t-1)| <= tol N the fit
+                             keeps theta_t+1 and skips the iterations left
+                             (on the device, no host synchronisation): their
+                             loglik entries are NaN, loglik[iters] is
+                             L(theta_t+1).  Batched and 4D fits need 0.    */
 } gmm_fit_opts;
 
 /* Short text of a status code (static storage). */
@@ -203,8 +215,19 @@ gmm_status gmm_loglik_backward(const float *pts, int64_t n, const float *pose6,
  *  w, mu, cov   device float32 sum K_f, x 3, x 3 x 3 (concatenated).
  *  loglik       device float64 B x (iters + 1) (row f = frame f), or NULL.
  * Every frame follows gmm_fit exactly (same E-step, M-step and per-frame
- * reductions); the frames' work is spread over the GPU by one launch per
- * M-phase class and iteration, with the whole loop captured in a hipGraph.
+ * reductions); a pass over all frames is one tile launch per M-phase class
+ * (cost-balanced per-block segments of the frames' tiles), then one
+ * reduction and one update launch, with the whole loop captured in a
+ * hipGraph.  Launch shape of the soft passes: dense tiles of 64 points with
+ * 512 or 1024 threads per block ("bb512", "bb1024"), or culled tiles
+ * of 128 points in each frame's Morton order, skipping (tile, component)
+ * pairs whose FP32 weights are exactly zero as gmm_fit does ("bc512p8s32",
+ * "bc512p8s64", "bc512p16s64").  Default "bb512"; GMM_BATCH_SHAPE=<name>
+ * forces one; with autotuning on (gmm_set_autotune), the first call for a
+ * new (device, B, K_max, floor(log2 sum N_f K_f)) runs up to 4 EM
+ * iterations, times one soft pass of every shape on its own data at that
+ * point, keeps the fastest and restarts the fit with it (per process, and in
+ * GMM_AUTOTUNE_CACHE as "batch B K_max bucket name" lines).
  * Synchronises once (twice with the plan upload) unless GMM_FLAG_ASYNC.
  * Errors: as gmm_fit, per frame. */
 size_t gmm_fit_batched_workspace_size(int32_t B, const int64_t *pt_off,
@@ -216,6 +239,11 @@ gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
                            float *w, float *mu, float *cov, double *loglik,
                            const gmm_fit_opts *opts, void *ws, size_t ws_bytes,
                            void *stream);
+
+/* The soft-pass shape a gmm_fit_batched call with these frames would use
+ * now (static string; "" when autotuning is on and the batch is not tuned
+ * yet, or on bad arguments). */
+const char *gmm_fit_batched_config(int32_t B, const int64_t *pt_off, const int32_t *k_off);
 
 /* ------------------------------------------------------------ k-means++
  * Seeding of a fit: the paper starts EM from a randomised k-means step
@@ -247,6 +275,66 @@ gmm_status gmm_kmeanspp(const float *pts, int64_t n, int32_t k, const double *u,
                         int64_t *centres, int32_t *labels, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* ------------------------------------------- 4D model: position + intensity
+ * The paper's model (Sec. IV "GIRA Reconstruction"; Sec. V tensor shapes:
+ * weights (1, K, 1), means (1, K, 4), covariances (1, K, 4, 4)) is a
+ * mixture over 4D points (x, y, z, intensity); its size is
+ * 4 K (1 + 4 + 10) bytes in float32.
+ *
+ * gmm4_fit: fixed-iteration EM of the 4D mixture, exactly as gmm_fit with
+ * D = 4 (eq. 1-3 with D ln 2pi / 2 = 2 ln 2pi; M-step N_b = sum g + 10
+ * DBL_EPSILON, pi_b = N_b / sum N, mu_b = sum g x / N_b, Sigma_b = sum g
+ * (x - mu)(x - mu)^T / N_b + lambda I; FP32 E-step, FP64 sums, FP64 4 x 4
+ * Cholesky).  Every tile of 64 points is evaluated against every component
+ * (no spatial ordering or skipping).
+ *  pts          device float32 N x 4 (x, y, z, intensity), 16-byte aligned.
+ *  init_labels  device int32 N in [0, K), or NULL (then w/mu/cov hold
+ *               theta_0 on entry, weights used as given).
+ *  w, mu, cov   device float32 K, K x 4, K x 4 x 4 (lower triangle read,
+ *               symmetric written); theta_T on return.
+ *  loglik       device float64 iters + 1 entries, or NULL (as gmm_fit).
+ *  1 <= K <= 512, K <= N.  Synchronises once unless GMM_FLAG_ASYNC (then
+ *  the status word is at the start of ws: gmm_workspace_status).
+ *  Errors: as gmm_fit; points not 16-byte aligned are INVALID_ARG. */
+size_t gmm4_fit_workspace_size(int64_t n, int32_t k, const gmm_fit_opts *opts);
+gmm_status gmm4_fit(const float *pts, int64_t n, int32_t k, const int32_t *init_labels,
+                    float *w, float *mu, float *cov, double *loglik,
+                    const gmm_fit_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/* gmm4_color_conditional: expected intensity and its variance at known 3D
+ * locations (the paper's color_conditional).  Under the 4D mixture the
+ * intensity given x is a mixture of 1D Gaussians: weights beta_b(x)
+ * proportional to pi_b N(x | mu_b^x, Sigma_b^xx) (3D marginals), means
+ * m_b(x) = mu_b^i + Sigma_b^ix (Sigma_b^xx)^-1 (x - mu_b^x), variances
+ * v_b = Sigma_b^ii - Sigma_b^ix (Sigma_b^xx)^-1 Sigma_b^xi; expected[i] =
+ * sum_b beta_b m_b and variance[i] = sum_b beta_b (v_b + m_b^2) - E^2.
+ *  locs      device float32 M x 3;  expected, variance: device float32 M.
+ *  w, mu, cov  the 4D mixture as gmm4_fit returns it (w > 0).
+ *  FP32 per (location, component) terms, FP64 sums; FP64 Cholesky per
+ *  component.  Does not synchronise; device-side NOT_SPD / NONFINITE /
+ *  INVALID_ARG (w <= 0) via gmm_workspace_status(ws).  1 <= K <= 512. */
+size_t gmm4_color_conditional_workspace_size(int32_t k);
+gmm_status gmm4_color_conditional(const float *locs, int64_t m, int32_t k, const float *w,
+                                  const float *mu, const float *cov, float *expected,
+                                  float *variance, void *ws, size_t ws_bytes, void *stream);
+
+/* gmm4_joint_dist_sample: M samples of the 4D mixture (the paper's
+ * joint_dist_sample) from caller-given draws: sample s takes the first
+ * component whose running sum of the weights (component order, FP64)
+ * exceeds u[s] W, W the total (the last component with w > 0 when rounding
+ * leaves none), and is mu_b + L_b z[s] with Sigma_b = L_b L_b^T (FP64
+ * Cholesky, FP64 arithmetic, rounded to float32).
+ *  u     device float64 M in [0, 1);  z: device float32 M x 4 standard
+ *        normals;  out: device float32 M x 4;  comp: device int32 M (the
+ *        chosen components) or NULL.
+ *  w >= 0 with a positive total.  Does not synchronise; device-side errors
+ *  (a draw outside [0, 1), w < 0, a covariance not SPD) via
+ *  gmm_workspace_status(ws).  1 <= K <= GMM_MAX_K. */
+size_t gmm4_joint_dist_sample_workspace_size(int32_t k);
+gmm_status gmm4_joint_dist_sample(int32_t k, const float *w, const float *mu, const float *cov,
+                                  int64_t m, const double *u, const float *z, float *out,
+                                  int32_t *comp, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------ autotuning
  * With autotuning on (gmm_set_autotune(1), or GMM_AUTOTUNE=1 in the
  * environment), the first gmm_fit for a new (device arch, K, N bucket =
@@ -262,13 +350,14 @@ const char *gmm_tile_config(int64_t n, int32_t k);
 
 /* ------------------------------------------------------------ profiling
  * Kernel timing for benchmarks.  While enabled (reps >= 1, per calling host
- * thread), every E+M statistics pass of the tile kernel made by gmm_fit is
- * launched reps times back to back between two HIP events recorded on the
- * caller's stream (such calls launch their kernels directly instead of
- * replaying a captured graph).  The tile kernel only reads the points and
- * parameters and overwrites its own partial sums, so the repeats change no
- * result; they spread the event pair's dispatch latency (a few
- * microseconds) over reps launches.  reps = 0 disables; reps > 64 is
+ * thread), every E+M statistics pass of the tile kernel made by gmm_fit, the
+ * tile pass of gmm_loglik and the backward tile kernel of
+ * gmm_loglik_backward are launched reps times back to back between two HIP
+ * events recorded on the caller's stream (such calls launch their kernels
+ * directly instead of replaying a captured graph).  These kernels only read
+ * the points and parameters and overwrite their own outputs and partial
+ * sums, so the repeats change no result; they spread the event pair's
+ * dispatch latency (a few microseconds) over reps launches.  reps = 0 disables; reps > 64 is
  * INVALID_ARG.  gmm_profile_read waits for the recorded events, returns the
  * summed elapsed time (ms) and the number of tile launches it covers since
  * the last read, and resets both.  Errors: DEVICE when an event call fails. */

@@ -14,7 +14,7 @@ import ctypes
 from . import _lib
 
 __all__ = ["fit", "fit_noalloc", "fit_batched", "loglik", "loglik_backward", "GMMLogLik",
-           "FitResult", "kmeanspp"]
+           "FitResult", "kmeanspp", "fit4", "color_conditional", "joint_dist_sample"]
 
 
 def _torch():
@@ -60,11 +60,13 @@ class FitResult:
 
 
 def fit(points, k, iters=100, reg_covar=1e-3, labels=None, theta0=None,
-        moment_mode="shifted", workspace=None, sync=True):
+        moment_mode="shifted", workspace=None, sync=True, tol=0.0):
     """EM fit of a K-component 3D GMM to ``points`` (float32 (N, 3), on GPU).
 
     Start either from hard ``labels`` (int32 (N,), values in [0, K)) whose
-    one-hot M-step gives theta_0, or from ``theta0 = (w, mu, cov)``."""
+    one-hot M-step gives theta_0, or from ``theta0 = (w, mu, cov)``.
+    ``tol`` > 0 stops early once the log-likelihood changes by at most
+    tol * N between iterations (the skipped iterations' L entries are NaN)."""
     torch = _torch()
     lib = _lib.load()
     pts = _check_points(points)
@@ -73,7 +75,7 @@ def fit(points, k, iters=100, reg_covar=1e-3, labels=None, theta0=None,
     opts = _lib.FitOpts(int(iters), float(reg_covar),
                         {"shifted": _lib.GMM_MOMENTS_SHIFTED,
                          "two_pass": _lib.GMM_MOMENTS_TWO_PASS}[moment_mode],
-                        0 if sync else _lib.GMM_FLAG_ASYNC)
+                        0 if sync else _lib.GMM_FLAG_ASYNC, float(tol))
     if labels is not None:
         lab = labels.to(device=dev, dtype=torch.int32).contiguous()
         if lab.shape != (n,):
@@ -369,3 +371,112 @@ def kmeanspp(points, k, seed=0, u=None, workspace=None):
                                 0 if workspace is None else workspace.numel(),
                                 _stream(dev)))
     return labels, centres
+
+
+# ------------------------------------------------------------- 4D model
+
+def fit4(points, k, iters=100, reg_covar=1e-3, labels=None, theta0=None,
+         moment_mode="shifted", sync=True):
+    """EM fit of a K-component 4D mixture to ``points`` (float32 (N, 4) =
+    (x, y, z, intensity) on the GPU); start from hard ``labels`` or from
+    ``theta0 = (w (K,), mu (K, 4), cov (K, 4, 4))``.  Returns a FitResult
+    with means (K, 4) and covariances (K, 4, 4)."""
+    torch = _torch()
+    lib = _lib.load()
+    if not isinstance(points, torch.Tensor) or not points.is_cuda:
+        raise TypeError("points must be a CUDA (HIP) torch tensor")
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 4:
+        raise ValueError("points must be float32 of shape (N, 4)")
+    pts = points.contiguous()
+    dev = pts.device
+    n = pts.shape[0]
+    opts = _lib.FitOpts(int(iters), float(reg_covar),
+                        {"shifted": _lib.GMM_MOMENTS_SHIFTED,
+                         "two_pass": _lib.GMM_MOMENTS_TWO_PASS}[moment_mode],
+                        0 if sync else _lib.GMM_FLAG_ASYNC)
+    if labels is not None:
+        lab = labels.to(device=dev, dtype=torch.int32).contiguous()
+        if lab.shape != (n,):
+            raise ValueError("labels must have shape (N,)")
+        w = torch.empty(k, dtype=torch.float32, device=dev)
+        mu = torch.empty(k, 4, dtype=torch.float32, device=dev)
+        cov = torch.empty(k, 4, 4, dtype=torch.float32, device=dev)
+    elif theta0 is not None:
+        lab = None
+        w, mu, cov = (a.to(device=dev, dtype=torch.float32).contiguous().clone()
+                      for a in theta0)
+        if w.shape != (k,) or mu.shape != (k, 4) or cov.shape != (k, 4, 4):
+            raise ValueError("theta0 shapes must be (K,), (K,4), (K,4,4)")
+    else:
+        raise ValueError("give labels or theta0")
+    L = torch.empty(iters + 1, dtype=torch.float64, device=dev)
+    need = lib.gmm4_fit_workspace_size(n, k, ctypes.byref(opts))
+    if need == 0:
+        _lib.check(lib.gmm4_fit(None, n, k, None, None, None, None, None,
+                                ctypes.byref(opts), None, 0, None))
+    ws = _workspace(need, dev)
+    _lib.check(lib.gmm4_fit(_ptr(pts), n, k, _ptr(lab), _ptr(w), _ptr(mu), _ptr(cov),
+                            _ptr(L), ctypes.byref(opts), _ptr(ws), ws.numel(),
+                            _stream(dev)))
+    return FitResult(w, mu, cov, L)
+
+
+def _mixture4(w, mu, cov, dev):
+    torch = _torch()
+    w = w.to(device=dev, dtype=torch.float32).contiguous()
+    k = w.shape[0]
+    mu = mu.to(device=dev, dtype=torch.float32).contiguous()
+    cov = cov.to(device=dev, dtype=torch.float32).contiguous()
+    if mu.shape != (k, 4) or cov.shape != (k, 4, 4):
+        raise ValueError("a 4D mixture has w (K,), mu (K, 4), cov (K, 4, 4)")
+    return w, mu, cov, k
+
+
+def color_conditional(locs, w, mu, cov, check=True):
+    """Expected intensity and its variance at 3D locations ``locs`` (float32
+    (M, 3) on the GPU) under a 4D mixture: (E (M,), V (M,)) float32."""
+    torch = _torch()
+    lib = _lib.load()
+    locs = _check_points(locs)
+    dev = locs.device
+    m = locs.shape[0]
+    w, mu, cov, k = _mixture4(w, mu, cov, dev)
+    E = torch.empty(m, dtype=torch.float32, device=dev)
+    V = torch.empty(m, dtype=torch.float32, device=dev)
+    ws = _workspace(max(lib.gmm4_color_conditional_workspace_size(k), 256), dev)
+    _lib.check(lib.gmm4_color_conditional(_ptr(locs), m, k, _ptr(w), _ptr(mu), _ptr(cov),
+                                          _ptr(E), _ptr(V), _ptr(ws), ws.numel(),
+                                          _stream(dev)))
+    if check:
+        _device_status(ws, dev)
+    return E, V
+
+
+def joint_dist_sample(w, mu, cov, m, seed=0, u=None, z=None, check=True):
+    """m samples (float32 (m, 4)) of a 4D mixture and their components
+    (int32 (m,)).  The draws: u (m,) uniforms in [0, 1) choose the component,
+    z (m, 4) standard normals the offset; by default both come from
+    numpy's default_rng(seed) (u first, then z)."""
+    import numpy as np
+    torch = _torch()
+    lib = _lib.load()
+    dev = torch.device("cuda", torch.cuda.current_device()) if not hasattr(w, "device") \
+        else w.device
+    w, mu, cov, k = _mixture4(w, mu, cov, dev)
+    if u is None or z is None:
+        rng = np.random.default_rng(seed)
+        u = rng.random(m) if u is None else u
+        z = rng.standard_normal((m, 4)) if z is None else z
+    u = torch.as_tensor(np.asarray(u, np.float64)).to(dev)
+    z = torch.as_tensor(np.asarray(z, np.float32)).to(dev).contiguous()
+    if u.shape != (m,) or z.shape != (m, 4):
+        raise ValueError("u must be (m,) and z (m, 4)")
+    out = torch.empty(m, 4, dtype=torch.float32, device=dev)
+    comp = torch.empty(m, dtype=torch.int32, device=dev)
+    ws = _workspace(max(lib.gmm4_joint_dist_sample_workspace_size(k), 256), dev)
+    _lib.check(lib.gmm4_joint_dist_sample(k, _ptr(w), _ptr(mu), _ptr(cov), m, _ptr(u),
+                                          _ptr(z), _ptr(out), _ptr(comp), _ptr(ws),
+                                          ws.numel(), _stream(dev)))
+    if check:
+        _device_status(ws, dev)
+    return out, comp

@@ -16,6 +16,7 @@ GMM_OK = 0
 GMM_MOMENTS_SHIFTED = 0
 GMM_MOMENTS_TWO_PASS = 1
 GMM_FLAG_ASYNC = 1
+GMM_FLAG_DETERMINISTIC = 2
 GMM_MAX_K = 1024
 GMM_FIT_NOALLOC_MAX_BYTES = 64 << 20
 
@@ -24,10 +25,13 @@ EXPORTS = (
     "gmm_fit_workspace_size", "gmm_fit", "gmm_fit_noalloc",
     "gmm_loglik_workspace_size", "gmm_loglik",
     "gmm_loglik_backward_workspace_size", "gmm_loglik_backward",
-    "gmm_fit_batched_workspace_size", "gmm_fit_batched",
+    "gmm_fit_batched_workspace_size", "gmm_fit_batched", "gmm_fit_batched_config",
     "gmm_set_autotune", "gmm_tile_config",
     "gmm_profile_enable", "gmm_profile_read", "gmm_profile_pairs",
     "gmm_kmeanspp_workspace_size", "gmm_kmeanspp",
+    "gmm4_fit_workspace_size", "gmm4_fit",
+    "gmm4_color_conditional_workspace_size", "gmm4_color_conditional",
+    "gmm4_joint_dist_sample_workspace_size", "gmm4_joint_dist_sample",
 )
 
 
@@ -39,7 +43,8 @@ class GmmError(RuntimeError):
 
 class FitOpts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("reg_covar", ctypes.c_double),
-                ("moment_mode", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("moment_mode", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("tol", ctypes.c_double)]
 
 
 _lib = None
@@ -87,6 +92,9 @@ def load():
         i32, vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
         vp, vp, vp, vp, vp, ctypes.POINTER(FitOpts), vp, sz, vp]
     lib.gmm_fit_batched.restype = ctypes.c_int
+    lib.gmm_fit_batched_config.argtypes = [
+        i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+    lib.gmm_fit_batched_config.restype = ctypes.c_char_p
     lib.gmm_set_autotune.argtypes = [ctypes.c_int]
     lib.gmm_set_autotune.restype = ctypes.c_int
     lib.gmm_tile_config.argtypes = [i64, i32]
@@ -103,6 +111,19 @@ def load():
     lib.gmm_kmeanspp_workspace_size.restype = sz
     lib.gmm_kmeanspp.argtypes = [vp, i64, i32, vp, vp, vp, vp, sz, vp]
     lib.gmm_kmeanspp.restype = ctypes.c_int
+    lib.gmm4_fit_workspace_size.argtypes = [i64, i32, ctypes.POINTER(FitOpts)]
+    lib.gmm4_fit_workspace_size.restype = sz
+    lib.gmm4_fit.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp,
+                             ctypes.POINTER(FitOpts), vp, sz, vp]
+    lib.gmm4_fit.restype = ctypes.c_int
+    lib.gmm4_color_conditional_workspace_size.argtypes = [i32]
+    lib.gmm4_color_conditional_workspace_size.restype = sz
+    lib.gmm4_color_conditional.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.gmm4_color_conditional.restype = ctypes.c_int
+    lib.gmm4_joint_dist_sample_workspace_size.argtypes = [i32]
+    lib.gmm4_joint_dist_sample_workspace_size.restype = sz
+    lib.gmm4_joint_dist_sample.argtypes = [i32, vp, vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
+    lib.gmm4_joint_dist_sample.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -144,3 +165,17 @@ def set_autotune(on: bool) -> None:
 def tile_config(n: int, k: int) -> str:
     """Name of the tile shape a fit of n points, k components uses now."""
     return load().gmm_tile_config(int(n), int(k)).decode()
+
+
+def batch_config(ns, ks) -> str:
+    """Soft-pass shape of a batched fit of frames with ns points and ks
+    components ("" when autotuning will pick it at the call)."""
+    import numpy as np
+    B = len(ns)
+    pt_off = np.zeros(B + 1, np.int64)
+    pt_off[1:] = np.cumsum(ns)
+    k_off = np.zeros(B + 1, np.int32)
+    k_off[1:] = np.cumsum(ks)
+    return load().gmm_fit_batched_config(
+        B, pt_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        k_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))).decode()

@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "gmm.hip")
+SRCS = [os.path.join(HERE, "csrc", "gmm.hip"), os.path.join(HERE, "csrc", "gmm4.hip")]
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmm.so")
 ARCH = "gfx950"
@@ -28,7 +28,7 @@ def hipcc() -> str:
 def build(verbose: bool = False, extra=None) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *(extra or []), "-o", tmp, SRC]
+           *(extra or []), "-o", tmp, *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

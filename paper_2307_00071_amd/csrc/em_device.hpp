@@ -550,6 +550,8 @@ struct TileArgs {
   // kernel timing only: the culled kernel adds the (tile, component) pairs
   // it evaluated here; NULL otherwise
   unsigned long long *pairs = nullptr;
+  // fits with a tolerance: bit 0 set = converged, the pass does nothing
+  const unsigned *conv = nullptr;
 };
 
 #ifndef GMM_TILE_WPE
@@ -568,6 +570,7 @@ __attribute__((amdgpu_waves_per_eu(GMM_TILE_WPE, 8))) void em_tile_kernel(
   constexpr int G = S::G, TS = S::TS;
   constexpr int trip = TRIP;
   extern __shared__ __align__(16) unsigned char smem[];
+  if (a.conv && (*a.conv & 1u)) return;   // converged fit: nothing to do
   const int K = a.K, KC = a.KC, P = a.P, mode = a.mode;
   float *E = reinterpret_cast<float *>(smem);
   float4 *Xs = reinterpret_cast<float4 *>(smem + tile_lds_bytes_e<BLOCK, T>(K, KC));
@@ -1329,6 +1332,7 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
     float *__restrict__ lse_out,       // N or NULL
     TileArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (a.conv && (*a.conv & 1u)) return;   // converged fit: nothing to do
   const CullLds L = cull_carve<BLOCK, T, TRIP, SCAP, CPR>(smem, a.K);
   cull_begin<BLOCK, CPR>(L, cpar, shift, a.K);
   double Lacc = 0.0;
@@ -1361,7 +1365,8 @@ constexpr int kUpdThreads = 1024;
 template <int NT>
 __global__ __launch_bounds__(NT) void reduce_rows_kernel(
     const double *__restrict__ part, int nrows, int ncols, int col0,
-    double *__restrict__ red2) {
+    double *__restrict__ red2, const unsigned *conv = nullptr) {
+  if (conv && (*conv & 1u)) return;   // converged fit: nothing to do
   constexpr int NW = NT / 64;
   __shared__ double sh[NW][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1395,6 +1400,7 @@ __global__ __launch_bounds__(NT) void reduce_rows_kernel(
 struct UpdArgs {
   int ncols, col0, K, mode, umode;
   double reg;
+  double tol_abs;   // > 0: stop once |L(theta_t) - L(theta_t-1)| <= tol_abs
 };
 struct UpdPtrs {
   const double *red2;
@@ -1406,6 +1412,9 @@ struct UpdPtrs {
   double *loglik_slot;
   float *out_w, *out_mu, *out_cov;
   uint32_t *status;
+  // fits with a tolerance: [0] bit 0 converged, bit 1 L_prev valid; the
+  // double at [2] holds L_prev.  NULL otherwise.
+  unsigned *conv = nullptr;
 };
 
 // tot = the column sums of red2 (LDS), the log-likelihood slot, then the
@@ -1414,6 +1423,16 @@ __device__ __forceinline__ void update_body(const UpdPtrs &q, const UpdArgs &a,
                                             unsigned char *smem) {
   const int tid = threadIdx.x;
   const int K = a.K;
+  if (q.conv && (*q.conv & 1u)) {
+    // converged: the iterations left are not run (their L is NaN); the
+    // parameters carry over to the set the next pass reads
+    if (tid == 0 && q.loglik_slot) q.loglik_slot[0] = (double)NAN;
+    if (a.umode != kUpdNone) {
+      for (int i = tid; i < (K + 1) * kParStride; i += kUpdThreads) q.cpar_out[i] = q.cpar_in[i];
+      for (int b = tid; b < K; b += kUpdThreads) q.shift_out[b] = q.shift_in[b];
+    }
+    return;
+  }
   double *tot = reinterpret_cast<double *>(smem);  // ncols
   double *scratch = tot + a.ncols;                 // 2 kUpdThreads / 64 + 2
   // four columns per thread at a time: all 16 loads in flight
@@ -1445,6 +1464,16 @@ __device__ __forceinline__ void update_body(const UpdPtrs &q, const UpdArgs &a,
     em_update_block<kUpdThreads>(tot, K, a.umode, a.reg, q.cpar_in, q.shift_in,
                                  q.cpar_out, q.shift_out, q.th64, scratch,
                                  q.status);
+    // stopping rule, after a full M-step: theta_(t+1) is kept and the
+    // following iterations are skipped once L changed by at most tol_abs
+    if (tid == 0 && q.conv && a.umode == kUpdFull && a.mode == kSoftStats) {
+      const double L = tot[kNStat * K];
+      double *Lprev = reinterpret_cast<double *>(q.conv + 2);
+      unsigned f = *q.conv;
+      if ((f & 2u) && fabs(L - *Lprev) <= a.tol_abs) f |= 1u;
+      *Lprev = L;
+      *q.conv = f | 2u;
+    }
   } else if (q.out_w) {
     for (int b = tid; b < K; b += kUpdThreads) {
       const double *t = q.th64 + (size_t)b * kTh64Stride;
@@ -1522,6 +1551,10 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_batch_kernel(
 }
 
 
+// Batched fits, dense: a block takes its segments (frame, tiles [t0, t1),
+// row) in order, each with that frame's K and point-subset split P; every
+// frame of one launch has the same TRIP = ceil(T / P) (LDS sized for the
+// launch's largest K).
 template <int BLOCK, int T, int TRIP>
 __global__ __launch_bounds__(BLOCK) void em_batch_kernel(
     const float4 *__restrict__ pts, const float *__restrict__ cpar_all,

@@ -21,13 +21,18 @@
 #include "kinit_device.hpp"
 #include "gmm.h"
 
+// Text of the last host-side error of this thread (shared by every
+// translation unit of the library; gmm_last_error returns it).
+namespace gmm_host {
+thread_local char g_err[512];
+}
+
 namespace {
 
 using namespace gmm_dev;
+using gmm_host::g_err;
 
 // ======================================================================= host
-
-thread_local char g_err[512];
 
 gmm_status fail(gmm_status s, const char *fmt, ...) {
   va_list ap;
@@ -450,6 +455,11 @@ bool make_cull_cfg(int K, int64_t n, CullCfg *out) {
   out->tile = T;
   out->trip = TRIP;
   out->grid = (int)std::min<int64_t>(ntiles, (int64_t)di.cus * per_cu);
+  // GMM_CULL_GRID=<blocks>: fewer persistent blocks (tuning experiments)
+  if (const char *g = getenv("GMM_CULL_GRID")) {
+    const int v = atoi(g);
+    if (v > 0 && v < out->grid) out->grid = v;
+  }
   out->lds = lds;
   out->launch = &launch_cull<BLOCK, T, TRIP, SCAP, CPR, false, false>;
   out->launch_lab = &launch_cull<BLOCK, T, TRIP, SCAP, CPR, true, false>;
@@ -550,7 +560,7 @@ WsLayout ws_layout(int64_t n, int K, const TileCfg &c, int extra_cols = 0,
   L.nslots = std::max(std::max(c.grid, grid_override), max_grid(K, n));
   L.npad = ((n + 255) / 256) * 256;   // a multiple of every tile size
   L.status = o; o = align256(o + 256);
-  L.counter = o; o = align256(o + sizeof(unsigned));
+  L.counter = o; o = align256(o + 4 * sizeof(unsigned));   // stopping rule state
   L.pose64 = o; o = align256(o + 32 * sizeof(double));
   L.rt32 = o; o = align256(o + 16 * sizeof(float));
   for (int i = 0; i < 2; ++i) {
@@ -602,6 +612,10 @@ gmm_status get_ws(void **ws, size_t *ws_bytes, size_t need, hipStream_t s,
                   WsGuard *g) {
   if (*ws == nullptr) {
     void *p = nullptr;
+    // GMM_FAULT_INJECT=oom: the allocation fails (tests of the error path)
+    const char *fi = getenv("GMM_FAULT_INJECT");
+    if (fi && strcmp(fi, "oom") == 0)
+      return fail(GMM_ERR_OOM, "hipMallocAsync(%zu) failed (GMM_FAULT_INJECT=oom)", need);
     if (hipMallocAsync(&p, need, s) != hipSuccess)
       return fail(GMM_ERR_OOM, "hipMallocAsync(%zu) failed", need);
     g->ptr = p;
@@ -635,6 +649,8 @@ struct Run {
   int K = 0;
   int cur = 0;   // parameter set the next pass reads
   std::vector<EventPair> *sink = nullptr;  // profiling pairs go here
+  bool time_loglik = false;  // also time log-likelihood-only passes
+  double tol_abs = 0.0;      // > 0: stopping rule |dL| <= tol_abs
 };
 
 // The tile kernel alone (writes the partial rows only).
@@ -698,9 +714,13 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   a.P = r.c.P;
   a.mode = mode;
   a.ncols = L.ncols;
+  // with a tolerance, the soft passes check the converged flag
+  unsigned *conv = (r.tol_abs > 0.0 && mode == kSoftStats) ? at<unsigned>(r.ws, L.counter)
+                                                          : nullptr;
+  a.conv = conv;
   const int rows = cull ? r.cc.grid : r.c.grid;  // partial rows written
   EventPair pp;
-  const bool timed = r.sink && mode == kSoftStats;
+  const bool timed = r.sink && (mode == kSoftStats || r.time_loglik);
   if (timed) {
     if (!make_pair(&pp)) return fail(GMM_ERR_DEVICE, "profiling event allocation failed");
     pp.reps = g_prof.reps;
@@ -732,7 +752,7 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   const int ncx = (L.ncols - col0 + 63) / 64;
   hipLaunchKernelGGL(reduce_rows_kernel<1024>, dim3(ncx, kRedChunksFit), dim3(1024), 0,
                      r.s, at<double>(r.ws, L.part), rows, L.ncols, col0,
-                     at<double>(r.ws, L.red));
+                     at<double>(r.ws, L.red), conv);
   HIP_TRY(hipGetLastError());
   UpdPtrs q;
   q.red2 = at<double>(r.ws, L.red);
@@ -746,6 +766,7 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   q.out_mu = out_mu;
   q.out_cov = out_cov;
   q.status = at<uint32_t>(r.ws, L.status);
+  q.conv = conv;
   UpdArgs ua;
   ua.ncols = L.ncols;
   ua.col0 = col0;
@@ -753,6 +774,7 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   ua.mode = mode;
   ua.umode = umode;
   ua.reg = reg;
+  ua.tol_abs = r.tol_abs;
   hipLaunchKernelGGL(update_kernel, dim3(1), dim3(kUpdThreads),
                      update_lds_bytes(r.K), r.s, q, ua);
   HIP_TRY(hipGetLastError());
@@ -763,7 +785,7 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
 gmm_status run_init(Run &r, bool zero_shift) {
   hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, r.s,
                      at<uint32_t>(r.ws, r.L.status),
-                     at<unsigned>(r.ws, r.L.counter), 1,
+                     at<unsigned>(r.ws, r.L.counter), 4,
                      zero_shift ? at<float4>(r.ws, r.L.shift[r.cur]) : nullptr,
                      r.K);
   HIP_TRY(hipGetLastError());
@@ -903,7 +925,11 @@ gmm_status fit_setup(const float *pts, int64_t n, int32_t k, const float *w,
   if (opts->moment_mode != GMM_MOMENTS_SHIFTED &&
       opts->moment_mode != GMM_MOMENTS_TWO_PASS)
     return fail(GMM_ERR_INVALID_ARG, "unknown moment_mode");
-  if (opts->flags & ~GMM_FLAG_ASYNC) return fail(GMM_ERR_INVALID_ARG, "unknown flags");
+  if (opts->flags & ~(GMM_FLAG_ASYNC | GMM_FLAG_DETERMINISTIC))
+    return fail(GMM_ERR_INVALID_ARG, "unknown flags");
+  if (!(opts->tol >= 0.0) || !isfinite(opts->tol))
+    return fail(GMM_ERR_INVALID_ARG, "tol must be finite and >= 0");
+  r->tol_abs = opts->tol * (double)n;
   r->K = k;
   if (!pick_cfg(k, n, &r->c)) return fail(GMM_ERR_UNSUPPORTED, "no launch configuration for k=%d", k);
   r->cull = pick_cull_cfg(k, n, &r->cc);
@@ -922,14 +948,14 @@ struct FitKey {
   const void *pts, *labels, *w, *mu, *cov, *loglik, *ws;
   int64_t n;
   size_t ws_bytes;
-  double reg;
+  double reg, tol;
   int k, iters, mode, dev;
   const void *dense, *culled;  // the kernels the fit launches
   bool sorted;
   bool operator==(const FitKey &o) const {
     return pts == o.pts && labels == o.labels && w == o.w && mu == o.mu &&
            cov == o.cov && loglik == o.loglik && ws == o.ws && n == o.n &&
-           ws_bytes == o.ws_bytes && reg == o.reg && k == o.k &&
+           ws_bytes == o.ws_bytes && reg == o.reg && tol == o.tol && k == o.k &&
            iters == o.iters && mode == o.mode && dev == o.dev &&
            dense == o.dense && culled == o.culled && sorted == o.sorted;
   }
@@ -994,36 +1020,94 @@ GraphEntry *graph_slot(const FitKey &key, bool *found) {
 
 
 // ============================================================ batched fits
+//
+// All frames' points are staged into 64-point tiles, each frame padded to a
+// multiple of 128 points (so the culled shapes' 128-point tiles never span
+// two frames).  A soft pass launches the tile kernel once per M-phase trip
+// class of the dense shapes (frames whose point-subset split gives the same
+// TRIP; LDS and grid sized for the class) or once for the culled shapes;
+// each launch cuts its frames' tiles into contiguous per-block ranges of
+// equal cost (tiles x K_f), split at frame boundaries into segments, and a
+// block writes one FP64 partial row per segment it touches.
+// reduce_frames_kernel and update_frames_kernel then finish every frame at
+// once; the whole T-iteration loop is captured into one hipGraph per call.
+// (One dense launch over all frames, with the trip chosen per segment and
+// LDS sized for the largest K, measured 3.5 ms per pass on the 64-frame
+// workload against about 1.2 ms for the class launches.)
+//
+// Launch shapes: dense 512- or 1024-thread blocks ("bb512", "bb1024"), or
+// the culled kernel (512 threads, 128-point tiles in each frame's own Morton
+// order) with (TRIP, SCAP) = (8, 32), (8, 64) or (16, 64).  Label passes
+// always use the dense 512 shape (1024 beyond 512 components).  With
+// autotuning on, the first batched fit for a new (device, B, K_max,
+// log2 sum N_f K_f) runs a few EM iterations, times one soft pass of every
+// runnable shape on the caller's own data and keeps the fastest (cached per
+// process and in GMM_AUTOTUNE_CACHE); GMM_BATCH_SHAPE forces a shape;
+// GMM_BATCH_CULL=1 selects the first culled shape; the default is the dense
+// 512 shape.
 
-constexpr int kBatchBlock = 512;
-constexpr int kBatchT = 64;
+constexpr int kBatchT = 64;        // dense tiles
+constexpr int kBatchTuneIters = 4; // EM iterations before the shapes are timed
+constexpr int kBatchCullT = 128;   // culled tiles; every frame is padded to this
+constexpr int kBatchMaxK = 512;    // largest K_f
 
-struct BatchClass {
+// One launch of a batched pass: its frames' segments (cost-balanced block
+// ranges), grid, LDS and kernel instance.
+struct BatchLaunchSet;
+using BatchLaunch = void (*)(const BatchLaunchSet &, hipStream_t, const float4 *,
+                             const float4 *, const float *, const float4 *, double *,
+                             const unsigned char *, size_t frames_off, int);
+
+struct BatchLaunchSet {
   int trip = 0, kc_max = 0, grid = 0;
   size_t lds = 0;
+  BatchLaunch launch = nullptr;
   std::vector<BSeg> segs;
-  std::vector<int> blk;   // grid + 1 segment offsets
-  size_t seg_off = 0, blk_off = 0;   // byte offsets in the plan upload
-  void (*launch)(const BatchClass &, hipStream_t, const float4 *, const float *,
-                 const float4 *, double *, const BFrame *, const BSeg *,
-                 const int *, int) = nullptr;
+  std::vector<int> blk;         // grid + 1 segment offsets
+  size_t seg_off = 0, blk_off = 0;   // in the plan upload
 };
 
-template <int TRIP>
-void launch_batch(const BatchClass &c, hipStream_t s, const float4 *pts,
-                  const float *cpar, const float4 *shift, double *part,
-                  const BFrame *frames, const BSeg *segs, const int *blk,
-                  int mode) {
-  hipLaunchKernelGGL((em_batch_kernel<kBatchBlock, kBatchT, TRIP>), dim3(c.grid),
-                     dim3(kBatchBlock), c.lds, s, pts, cpar, shift, part,
-                     frames, segs, blk, mode, c.kc_max);
+// A launch shape of the batched soft pass over every frame: the dense
+// kernel takes one launch per M-phase trip class (frames whose point-subset
+// split gives the same TRIP, LDS sized for the class's largest K), the
+// culled kernel one launch.
+struct BatchVariant {
+  int spec = -1;
+  std::vector<BFrame> frames;   // this shape's P, nrows and poff per frame
+  size_t frames_off = 0;
+  std::vector<BatchLaunchSet> sets;
+  int64_t part_len = 0;
+};
+
+template <int BLOCK, int TRIP>
+void launch_batch_dense(const BatchLaunchSet &c, hipStream_t s, const float4 *pts,
+                        const float4 *, const float *cpar, const float4 *shift,
+                        double *part, const unsigned char *plan, size_t frames_off, int mode) {
+  hipLaunchKernelGGL((em_batch_kernel<BLOCK, kBatchT, TRIP>), dim3(c.grid), dim3(BLOCK), c.lds,
+                     s, pts, cpar, shift, part,
+                     reinterpret_cast<const BFrame *>(plan + frames_off),
+                     reinterpret_cast<const BSeg *>(plan + c.seg_off),
+                     reinterpret_cast<const int *>(plan + c.blk_off), mode, c.kc_max);
 }
 
-bool batch_instance(int trip, decltype(BatchClass::launch) *fn, const void **kfn) {
-#define GMM_BATCH_CASE(TR)                                                    \
-  case TR:                                                                   \
-    *fn = &launch_batch<TR>;                                                 \
-    *kfn = reinterpret_cast<const void *>(&em_batch_kernel<kBatchBlock, kBatchT, TR>); \
+template <int TRIP, int SCAP>
+void launch_batch_cull(const BatchLaunchSet &c, hipStream_t s, const float4 *pts,
+                       const float4 *sph, const float *cpar, const float4 *shift,
+                       double *part, const unsigned char *plan, size_t frames_off, int mode) {
+  hipLaunchKernelGGL((em_cull_batch_kernel<512, kBatchCullT, TRIP, SCAP>), dim3(c.grid),
+                     dim3(512), c.lds, s, pts, sph, cpar, shift, part,
+                     reinterpret_cast<const BFrame *>(plan + frames_off),
+                     reinterpret_cast<const BSeg *>(plan + c.seg_off),
+                     reinterpret_cast<const int *>(plan + c.blk_off), mode, c.kc_max);
+}
+
+// The dense kernel instance of (BLOCK, TRIP): launcher and function.
+template <int BLOCK>
+bool dense_instance(int trip, BatchLaunch *fn, const void **kfn) {
+#define GMM_BATCH_CASE(TR)                                                             \
+  case TR:                                                                            \
+    *fn = &launch_batch_dense<BLOCK, TR>;                                              \
+    *kfn = reinterpret_cast<const void *>(&em_batch_kernel<BLOCK, kBatchT, TR>);       \
     return true;
   switch (trip) {
     GMM_BATCH_CASE(1) GMM_BATCH_CASE(2) GMM_BATCH_CASE(4) GMM_BATCH_CASE(5)
@@ -1034,29 +1118,45 @@ bool batch_instance(int trip, decltype(BatchClass::launch) *fn, const void **kfn
 #undef GMM_BATCH_CASE
 }
 
-// Host plan of a batched fit: frame table, per-class cost-balanced tile
-// ranges cut into per-frame segments, and the workspace layout.
-// The culled soft passes of a batched fit: one kernel instance, its own
-// cost-balanced segments over tiles of kBatchCullT points and its own frame
-// table (partial rows differ from the dense passes').
-constexpr int kBatchCullT = 128;
-constexpr int kBatchCullBlock = 512;
-struct BatchCull {
-  int grid = 0;
-  size_t lds = 0;
-  std::vector<BFrame> frames;
-  std::vector<BSeg> segs;
-  std::vector<int> blk;
-  size_t frames_off = 0, seg_off = 0, blk_off = 0;
+struct BatchSpec {
+  const char *name;
+  bool cull;
+  int block, tile;
+  // dense: the instance of a trip; culled: the one instance
+  bool (*instance)(int trip, BatchLaunch *fn, const void **kfn);
+  size_t (*lds)(int kmax);
+};
+
+template <int TRIP, int SCAP>
+bool cull_instance(int, BatchLaunch *fn, const void **kfn) {
+  *fn = &launch_batch_cull<TRIP, SCAP>;
+  *kfn = reinterpret_cast<const void *>(&em_cull_batch_kernel<512, kBatchCullT, TRIP, SCAP>);
+  return true;
+}
+
+size_t lds_dense512(int k) { return batch_lds_bytes<512, kBatchT>(k); }
+size_t lds_dense1024(int k) { return batch_lds_bytes<1024, kBatchT>(k); }
+size_t lds_c8s32(int k) { return cull_lds_bytes<512, kBatchCullT, 8, 32>(k); }
+size_t lds_c8s64(int k) { return cull_lds_bytes<512, kBatchCullT, 8, 64>(k); }
+size_t lds_c16s64(int k) { return cull_lds_bytes<512, kBatchCullT, 16, 64>(k); }
+
+constexpr int kNumBatchSpec = 5;
+const BatchSpec kBatchSpec[kNumBatchSpec] = {
+    {"bb512", false, 512, kBatchT, &dense_instance<512>, &lds_dense512},
+    {"bb1024", false, 1024, kBatchT, &dense_instance<1024>, &lds_dense1024},
+    {"bc512p8s32", true, 512, kBatchCullT, &cull_instance<8, 32>, &lds_c8s32},
+    {"bc512p8s64", true, 512, kBatchCullT, &cull_instance<8, 64>, &lds_c8s64},
+    {"bc512p16s64", true, 512, kBatchCullT, &cull_instance<16, 64>, &lds_c16s64},
 };
 
 struct BatchPlan {
   int B = 0, Ktot = 0, Kmax = 0, ncols_max = 0;
-  int64_t tiles = 0;   // staged tiles of kBatchT points (frames padded to kBatchCullT)
-  std::vector<BFrame> frames;
-  std::vector<BatchClass> classes;
-  bool cull = false, sort = false;
-  BatchCull cc;
+  int64_t tiles = 0;   // staged 64-point tiles (frames padded to 128 points)
+  int64_t evals = 0;   // sum N_f K_f
+  std::vector<BFrame> base;   // frame table of the reductions, updates and sort
+  std::vector<BatchVariant> vars;
+  int lab_var = -1, soft_var = -1;
+  bool sort = false;          // a culled shape is present: Morton order + spheres
   size_t plan_bytes = 0;
   // workspace offsets
   size_t status, plan, cpar[2], shift[2], th64, red, part, pts4, total;
@@ -1066,13 +1166,108 @@ struct BatchPlan {
   size_t red_len = 0, part_len = 0;
 };
 
+// Cost-balanced contiguous block ranges over the tiles of the frames fr
+// (tiles of `tile` points; cost = tiles x K_f), cut at frame boundaries into
+// segments; nrows counts each frame's segments (its partial rows).
+void cut_segments(const std::vector<BFrame> &frames, const std::vector<int> &fr, int tile,
+                  int grid, std::vector<int> &nrows, BatchLaunchSet *c) {
+  const int r = tile / kBatchT;
+  double cost = 0.0;
+  for (int f : fr) cost += (double)((frames[f].n + tile - 1) / tile) * frames[f].K;
+  const double target = cost / grid;
+  double acc = 0.0;
+  int blk = 0;
+  c->segs.clear();
+  c->blk.assign(1, 0);
+  for (int f : fr) {
+    const BFrame &F = frames[f];
+    const int64_t nt = (F.n + tile - 1) / tile;
+    const int64_t t0 = F.toff / r;
+    int64_t t = 0;
+    while (t < nt) {
+      const double room = (blk + 1) * target - acc;
+      int64_t take = (int64_t)std::ceil(room / F.K - 1e-9);
+      if (blk == grid - 1) take = nt - t;
+      take = std::max<int64_t>(1, std::min<int64_t>(take, nt - t));
+      c->segs.push_back(BSeg{f, (int)(t0 + t), (int)(t0 + t + take), nrows[f]++});
+      t += take;
+      acc += (double)take * F.K;
+      if (acc >= (blk + 1) * target - 1e-6 && blk < grid - 1) {
+        ++blk;
+        c->blk.push_back((int)c->segs.size());
+      }
+    }
+  }
+  while ((int)c->blk.size() < grid + 1) c->blk.push_back((int)c->segs.size());
+}
+
+// One shape over the frames: its frame table (P per frame), launches with
+// their segments, and the partial-row layout; false when it cannot run
+// these frames.
+bool make_variant(const BatchPlan &bp, int spec, int cus, size_t lds_max, BatchVariant *v) {
+  const BatchSpec &S = kBatchSpec[spec];
+  if (bp.Kmax > (S.cull ? 512 : S.block)) return false;
+  v->spec = spec;
+  v->frames = bp.base;
+  v->sets.clear();
+  std::vector<int> trips(bp.B, 0);
+  for (int f = 0; f < bp.B; ++f) {
+    BFrame &F = v->frames[f];
+    F.P = pick_subsets(S.block / F.K, kBatchT);
+    trips[f] = S.cull ? 0 : (kBatchT + F.P - 1) / F.P;
+  }
+  std::vector<int> classes = trips;
+  std::sort(classes.begin(), classes.end());
+  classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+  std::vector<int> nrows(bp.B, 0);
+  for (int tr : classes) {
+    BatchLaunchSet c;
+    c.trip = tr;
+    std::vector<int> fr;
+    for (int f = 0; f < bp.B; ++f)
+      if (trips[f] == tr) {
+        fr.push_back(f);
+        c.kc_max = std::max(c.kc_max, v->frames[f].K);
+      }
+    const void *kfn = nullptr;
+    if (!S.instance(tr, &c.launch, &kfn)) return false;
+    c.lds = S.lds(c.kc_max);
+    if (c.lds > (lds_max ? lds_max : 65536)) return false;
+    if (c.lds > 65536 &&
+        hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds) !=
+            hipSuccess)
+      return false;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, S.block, c.lds) !=
+            hipSuccess || per_cu <= 0)
+      return false;
+    int64_t ntile = 0;
+    for (int f : fr) ntile += (v->frames[f].n + S.tile - 1) / S.tile;
+    c.grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntile, (int64_t)cus * per_cu));
+    cut_segments(v->frames, fr, S.tile, c.grid, nrows, &c);
+    v->sets.push_back(std::move(c));
+  }
+  int64_t poff = 0;
+  for (int f = 0; f < bp.B; ++f) {
+    v->frames[f].nrows = nrows[f];
+    v->frames[f].poff = poff;
+    poff += (int64_t)nrows[f] * v->frames[f].ncols;
+  }
+  v->part_len = poff;
+  return true;
+}
+
+// The frames, the label shape and the soft shape(s): every runnable shape
+// when `all` (autotuning and workspace sizing), else the one named by
+// soft_spec (-1: the default).
 gmm_status make_batch_plan(int B, const int64_t *pt_off, const int32_t *k_off,
-                           BatchPlan *bp, bool want_cull = false) {
+                           BatchPlan *bp, bool all, int soft_spec = -1) {
   DevInfo di = dev_info();
   if (di.cus <= 0) return fail(GMM_ERR_DEVICE, "no HIP device");
   if (B <= 0) return fail(GMM_ERR_INVALID_ARG, "B=%d must be positive", B);
+  *bp = BatchPlan{};
   bp->B = B;
-  bp->frames.assign(B, BFrame{});
+  bp->base.assign(B, BFrame{});
   int64_t toff = 0;
   int cpoff = 0, roff = 0;
   for (int f = 0; f < B; ++f) {
@@ -1080,13 +1275,13 @@ gmm_status make_batch_plan(int B, const int64_t *pt_off, const int32_t *k_off,
     const int K = k_off[f + 1] - k_off[f];
     if (n <= 0 || K <= 0 || K > n)
       return fail(GMM_ERR_INVALID_ARG, "frame %d: n=%lld k=%d", f, (long long)n, K);
-    if (K > kBatchBlock) return fail(GMM_ERR_UNSUPPORTED, "frame %d: k=%d above %d", f, K, kBatchBlock);
-    BFrame &F = bp->frames[f];
+    if (K > kBatchMaxK) return fail(GMM_ERR_UNSUPPORTED, "frame %d: k=%d above %d", f, K, kBatchMaxK);
+    if (n > ((int64_t)1 << 30)) return fail(GMM_ERR_UNSUPPORTED, "frame %d: n=%lld too large", f, (long long)n);
+    BFrame &F = bp->base[f];
     F.K = K;
     F.koff = k_off[f] - k_off[0];
     F.cpoff = cpoff;
     cpoff += (K + 1) * kParStride;
-    F.P = pick_subsets(kBatchBlock / K, kBatchT);
     F.ncols = kNStat * K + 1;
     F.roff = roff;
     roff += F.ncols;
@@ -1095,154 +1290,46 @@ gmm_status make_batch_plan(int B, const int64_t *pt_off, const int32_t *k_off,
     toff += (n + kBatchCullT - 1) / kBatchCullT * (kBatchCullT / kBatchT);
     bp->Kmax = std::max(bp->Kmax, K);
     bp->ncols_max = std::max(bp->ncols_max, F.ncols);
+    bp->evals += n * K;
   }
   bp->Ktot = k_off[B] - k_off[0];
   bp->tiles = toff;
   bp->red_len = roff;
-  // classes by M-phase trip
-  std::vector<int> trips;
-  for (auto &F : bp->frames) {
-    const int tr = (kBatchT + F.P - 1) / F.P;
-    if (std::find(trips.begin(), trips.end(), tr) == trips.end()) trips.push_back(tr);
+  if (toff * kBatchT >= ((int64_t)1 << 31))
+    return fail(GMM_ERR_UNSUPPORTED, "%lld staged points above the batched limit", (long long)(toff * kBatchT));
+  // label shape: dense 512 (1024 above 512 components)
+  const int lab_spec = bp->Kmax <= 512 ? 0 : 1;
+  bp->vars.clear();
+  BatchVariant lv;
+  if (!make_variant(*bp, lab_spec, di.cus, di.lds_max, &lv))
+    return fail(GMM_ERR_UNSUPPORTED, "no batched launch configuration for K_max=%d", bp->Kmax);
+  bp->vars.push_back(std::move(lv));
+  bp->lab_var = 0;
+  bp->soft_var = 0;
+  const bool cull_ok = [] {
+    const char *off = getenv("GMM_CULL");
+    return !(off && off[0] == '0');
+  }() && B <= 256;
+  for (int s = 0; s < kNumBatchSpec; ++s) {
+    if (s == lab_spec) continue;
+    if (!all && s != soft_spec) continue;
+    if (kBatchSpec[s].cull && !cull_ok) continue;
+    BatchVariant v;
+    if (!make_variant(*bp, s, di.cus, di.lds_max, &v)) continue;
+    if (s == soft_spec) bp->soft_var = (int)bp->vars.size();
+    bp->vars.push_back(std::move(v));
   }
-  std::sort(trips.begin(), trips.end());
-  std::vector<int> nrows(B, 0);
-  for (int tr : trips) {
-    BatchClass c;
-    c.trip = tr;
-    std::vector<int> fr;
-    for (int f = 0; f < B; ++f)
-      if ((kBatchT + bp->frames[f].P - 1) / bp->frames[f].P == tr) {
-        fr.push_back(f);
-        c.kc_max = std::max(c.kc_max, bp->frames[f].K);
-      }
-    c.lds = batch_lds_bytes<kBatchBlock, kBatchT>(c.kc_max);
-    const void *kfn = nullptr;
-    if (!batch_instance(tr, &c.launch, &kfn)) return fail(GMM_ERR_UNSUPPORTED, "no batch kernel for trip %d", tr);
-    if (c.lds > 65536 &&
-        hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds) != hipSuccess)
-      return fail(GMM_ERR_DEVICE, "LDS attribute");
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kBatchBlock, c.lds) != hipSuccess || per_cu <= 0)
-      return fail(GMM_ERR_DEVICE, "occupancy query failed");
-    int64_t ctiles = 0;
-    double cost = 0.0;
-    for (int f : fr) {
-      const int64_t nt = (pt_off[f + 1] - pt_off[f] + kBatchT - 1) / kBatchT;
-      ctiles += nt;
-      cost += (double)nt * bp->frames[f].K;
-    }
-    c.grid = (int)std::min<int64_t>(ctiles, (int64_t)di.cus * per_cu);
-    // walk the class's tiles, cutting block ranges at equal cost
-    const double target = cost / c.grid;
-    double acc = 0.0;
-    int blk = 0;
-    c.blk.push_back(0);
-    for (int f : fr) {
-      const BFrame &F = bp->frames[f];
-      const int64_t nt = (pt_off[f + 1] - pt_off[f] + kBatchT - 1) / kBatchT;
-      int64_t t = 0;
-      while (t < nt) {
-        // tiles this block can still take before reaching its cut
-        const double room = (blk + 1) * target - acc;
-        int64_t take = (int64_t)std::ceil(room / F.K - 1e-9);
-        if (blk == c.grid - 1) take = nt - t;
-        take = std::max<int64_t>(1, std::min<int64_t>(take, nt - t));
-        c.segs.push_back(BSeg{f, (int)(F.toff + t), (int)(F.toff + t + take), nrows[f]++});
-        t += take;
-        acc += (double)take * F.K;
-        if (acc >= (blk + 1) * target - 1e-6 && blk < c.grid - 1) {
-          ++blk;
-          c.blk.push_back((int)c.segs.size());
-        }
-      }
-    }
-    while ((int)c.blk.size() < c.grid + 1) c.blk.push_back((int)c.segs.size());
-    bp->classes.push_back(std::move(c));
-  }
-  int64_t poff = 0;
-  for (int f = 0; f < B; ++f) {
-    bp->frames[f].nrows = nrows[f];
-    bp->frames[f].poff = poff;
-    poff += (int64_t)nrows[f] * bp->frames[f].ncols;
-  }
-  bp->part_len = poff;
-  // culled soft passes: segments over tiles of kBatchCullT points
-  bp->cull = want_cull && B <= 256 && bp->Kmax <= kBatchCullBlock;
-  if (bp->cull) {
-    BatchCull &cc = bp->cc;
-    using Kern = decltype(&em_cull_batch_kernel<kBatchCullBlock, kBatchCullT, 8, 32>);
-    const Kern kfn = &em_cull_batch_kernel<kBatchCullBlock, kBatchCullT, 8, 32>;
-    cc.lds = cull_lds_bytes<kBatchCullBlock, kBatchCullT, 8, 32>(bp->Kmax);
-    int per_cu = 0;
-    if (cc.lds > (di.lds_max ? di.lds_max : 65536) ||
-        (cc.lds > 65536 &&
-         hipFuncSetAttribute(reinterpret_cast<const void *>(kfn),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)cc.lds) != hipSuccess) ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kfn),
-                                                     kBatchCullBlock, cc.lds) != hipSuccess ||
-        per_cu <= 0) {
-      bp->cull = false;
-    } else {
-      const int r = kBatchCullT / kBatchT;
-      int64_t ctiles = 0;
-      double cost = 0.0;
-      for (int f = 0; f < B; ++f) {
-        const int64_t nt = (bp->frames[f].n + kBatchCullT - 1) / kBatchCullT;
-        ctiles += nt;
-        cost += (double)nt * bp->frames[f].K;
-      }
-      cc.grid = (int)std::min<int64_t>(ctiles, (int64_t)di.cus * per_cu);
-      const double target = cost / cc.grid;
-      double acc = 0.0;
-      int blk = 0;
-      std::vector<int> cn(B, 0);
-      cc.blk.push_back(0);
-      for (int f = 0; f < B; ++f) {
-        const BFrame &F = bp->frames[f];
-        const int64_t nt = (F.n + kBatchCullT - 1) / kBatchCullT;
-        const int64_t t0 = F.toff / r;
-        int64_t t = 0;
-        while (t < nt) {
-          const double room = (blk + 1) * target - acc;
-          int64_t take = (int64_t)std::ceil(room / F.K - 1e-9);
-          if (blk == cc.grid - 1) take = nt - t;
-          take = std::max<int64_t>(1, std::min<int64_t>(take, nt - t));
-          cc.segs.push_back(BSeg{f, (int)(t0 + t), (int)(t0 + t + take), cn[f]++});
-          t += take;
-          acc += (double)take * F.K;
-          if (acc >= (blk + 1) * target - 1e-6 && blk < cc.grid - 1) {
-            ++blk;
-            cc.blk.push_back((int)cc.segs.size());
-          }
-        }
-      }
-      while ((int)cc.blk.size() < cc.grid + 1) cc.blk.push_back((int)cc.segs.size());
-      cc.frames = bp->frames;
-      int64_t cpo = 0;
-      for (int f = 0; f < B; ++f) {
-        cc.frames[f].nrows = cn[f];
-        cc.frames[f].poff = cpo;
-        cpo += (int64_t)cn[f] * cc.frames[f].ncols;
-      }
-      bp->part_len = std::max<int64_t>(bp->part_len, cpo);
-    }
-  }
-  // plan upload layout
+  for (const auto &v : bp->vars) bp->sort = bp->sort || kBatchSpec[v.spec].cull;
+  bp->part_len = 0;
+  for (const auto &v : bp->vars) bp->part_len = std::max<int64_t>(bp->part_len, v.part_len);
+  // plan upload: the base frame table, then each shape's tables
   size_t o = align256(sizeof(BFrame) * B);
-  for (auto &c : bp->classes) {
-    c.seg_off = o;
-    o = align256(o + sizeof(BSeg) * c.segs.size());
-    c.blk_off = o;
-    o = align256(o + sizeof(int) * c.blk.size());
-  }
-  if (bp->cull) {
-    bp->cc.frames_off = o;
-    o = align256(o + sizeof(BFrame) * B);
-    bp->cc.seg_off = o;
-    o = align256(o + sizeof(BSeg) * bp->cc.segs.size());
-    bp->cc.blk_off = o;
-    o = align256(o + sizeof(int) * bp->cc.blk.size());
+  for (auto &v : bp->vars) {
+    v.frames_off = o; o = align256(o + sizeof(BFrame) * B);
+    for (auto &c : v.sets) {
+      c.seg_off = o; o = align256(o + sizeof(BSeg) * c.segs.size());
+      c.blk_off = o; o = align256(o + sizeof(int) * c.blk.size());
+    }
   }
   bp->plan_bytes = o;
   // workspace
@@ -1258,10 +1345,9 @@ gmm_status make_batch_plan(int B, const int64_t *pt_off, const int32_t *k_off,
   bp->red = o; o = align256(o + bp->red_len * sizeof(double));
   bp->part = o; o = align256(o + bp->part_len * sizeof(double));
   bp->pts4 = o; o = align256(o + (size_t)bp->tiles * kBatchT * sizeof(float4));
-  if (bp->cull) {
+  if (bp->sort) {
     const size_t np = (size_t)bp->tiles * kBatchT;
     bp->tsph = o; o = align256(o + np / kBatchCullT * sizeof(float4));
-    bp->sort = true;
     bp->sort_blocks = (int)((np + kSortChunk - 1) / kSortChunk);
     bp->raw4 = o; o = align256(o + np * sizeof(float4));
     for (int i = 0; i < 2; ++i) {
@@ -1276,15 +1362,85 @@ gmm_status make_batch_plan(int B, const int64_t *pt_off, const int32_t *k_off,
   return GMM_OK;
 }
 
-// Culled batched passes only with GMM_BATCH_CULL=1 (and not GMM_CULL=0):
-// on subsampled frames a 128-point tile spans a large area, culling removes
-// little and the dense batch kernel is faster (64 frames of 20k..300k
-// depth points, T = 20: 30 ms dense, 40 ms culled).
-bool batch_cull_wanted() {
+int batch_spec_by_name(const char *name) {
+  for (int s = 0; s < kNumBatchSpec; ++s)
+    if (strcmp(kBatchSpec[s].name, name) == 0) return s;
+  return -1;
+}
+
+// The soft shape a call would use without tuning: GMM_BATCH_SHAPE, then
+// GMM_BATCH_CULL=1 (first culled shape), else the label shape.
+int batch_default_spec(int kmax) {
+  const char *e = getenv("GMM_BATCH_SHAPE");
+  if (e && *e) {
+    const int s = batch_spec_by_name(e);
+    if (s >= 0) return s;
+  }
   const char *off = getenv("GMM_CULL");
-  if (off && off[0] == '0') return false;
   const char *on = getenv("GMM_BATCH_CULL");
-  return on && on[0] == '1';
+  if (on && on[0] == '1' && !(off && off[0] == '0')) return 2;
+  return kmax <= 512 ? 0 : 1;
+}
+
+// ---- batched autotuner: per (device, B, K_max, log2 sum N_f K_f)
+struct BatchTune {
+  int dev, B, kmax, bucket, spec;
+};
+std::mutex g_btune_mu;
+std::vector<BatchTune> g_btune;
+bool g_btune_loaded = false;
+
+int evals_bucket(int64_t e) {
+  int b = 0;
+  while (e > 1) { e >>= 1; ++b; }
+  return b;
+}
+
+void btune_load_locked() {
+  if (g_btune_loaded) return;
+  g_btune_loaded = true;
+  const char *path = getenv("GMM_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE *f = fopen(path, "r");
+  if (!f) return;
+  char tag[16], name[64];
+  int B, kmax, bucket;
+  while (fscanf(f, "%15s", tag) == 1) {
+    if (strcmp(tag, "batch") == 0 && fscanf(f, "%d %d %d %63s", &B, &kmax, &bucket, name) == 4) {
+      const int s = batch_spec_by_name(name);
+      if (s >= 0) g_btune.push_back(BatchTune{-1, B, kmax, bucket, s});
+    } else {
+      int c;
+      while ((c = fgetc(f)) != EOF && c != '\n') {}
+    }
+  }
+  fclose(f);
+}
+
+int btune_lookup(const BatchPlan &bp) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_btune_mu);
+  btune_load_locked();
+  const int bucket = evals_bucket(bp.evals);
+  for (const auto &t : g_btune)
+    if ((t.dev == dev || t.dev == -1) && t.B == bp.B && t.kmax == bp.Kmax && t.bucket == bucket)
+      return t.spec;
+  return -1;
+}
+
+void btune_store(const BatchPlan &bp, int spec) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_btune_mu);
+  const int bucket = evals_bucket(bp.evals);
+  g_btune.push_back(BatchTune{dev, bp.B, bp.Kmax, bucket, spec});
+  const char *path = getenv("GMM_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE *f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "batch %d %d %d %s\n", bp.B, bp.Kmax, bucket, kBatchSpec[spec].name);
+  fclose(f);
 }
 
 // Every frame of the staged batch in its own Morton order: raw4 -> pts4.
@@ -1328,7 +1484,17 @@ struct BatchRun {
   void *ws = nullptr;
   hipStream_t s = nullptr;
   int cur = 0;
+  bool timed = false;   // profiling: time the soft passes' tile launches
 };
+
+// The tile launch of one pass with shape variant v.
+void batch_tiles(BatchRun &r, const BatchVariant &v, int mode) {
+  const BatchPlan &bp = *r.bp;
+  for (const auto &c : v.sets)
+    c.launch(c, r.s, at<float4>(r.ws, bp.pts4), bp.sort ? at<float4>(r.ws, bp.tsph) : nullptr,
+             at<float>(r.ws, bp.cpar[r.cur]), at<float4>(r.ws, bp.shift[r.cur]),
+             at<double>(r.ws, bp.part), at<unsigned char>(r.ws, bp.plan), v.frames_off, mode);
+}
 
 gmm_status batch_pass(BatchRun &r, int mode, int umode, double reg,
                       double *loglik, int ll_stride, int ll_index,
@@ -1336,26 +1502,26 @@ gmm_status batch_pass(BatchRun &r, int mode, int umode, double reg,
                       float *out_cov = nullptr) {
   const BatchPlan &bp = *r.bp;
   unsigned char *plan = at<unsigned char>(r.ws, bp.plan);
-  const bool cull = bp.cull && mode != kLabels;
-  const BFrame *frames = reinterpret_cast<const BFrame *>(plan + (cull ? bp.cc.frames_off : 0));
-  if (cull) {
-    hipLaunchKernelGGL((em_cull_batch_kernel<kBatchCullBlock, kBatchCullT, 8, 32>),
-                       dim3(bp.cc.grid), dim3(kBatchCullBlock), bp.cc.lds, r.s,
-                       at<float4>(r.ws, bp.pts4), at<float4>(r.ws, bp.tsph),
-                       at<float>(r.ws, bp.cpar[r.cur]), at<float4>(r.ws, bp.shift[r.cur]),
-                       at<double>(r.ws, bp.part), frames,
-                       reinterpret_cast<const BSeg *>(plan + bp.cc.seg_off),
-                       reinterpret_cast<const int *>(plan + bp.cc.blk_off), mode, bp.Kmax);
-    HIP_TRY(hipGetLastError());
-  } else {
-    for (const auto &c : bp.classes) {
-      c.launch(c, r.s, at<float4>(r.ws, bp.pts4), at<float>(r.ws, bp.cpar[r.cur]),
-               at<float4>(r.ws, bp.shift[r.cur]), at<double>(r.ws, bp.part), frames,
-               reinterpret_cast<const BSeg *>(plan + c.seg_off),
-               reinterpret_cast<const int *>(plan + c.blk_off), mode);
-      HIP_TRY(hipGetLastError());
-    }
+  const BatchVariant &v = bp.vars[mode == kLabels ? bp.lab_var : bp.soft_var];
+  const BFrame *frames = reinterpret_cast<const BFrame *>(plan + v.frames_off);
+  const bool timed = r.timed && mode == kSoftStats;
+  EventPair pp;
+  if (timed) {
+    if (!make_pair(&pp)) return fail(GMM_ERR_DEVICE, "profiling event allocation failed");
+    pp.reps = g_prof.reps;
+    g_prof.pending.push_back(pp);
+    int64_t pairs = 0;
+    for (const auto &F : v.frames)
+      pairs += (int64_t)((F.n + kBatchT - 1) / kBatchT) * F.K;
+    g_prof.pairs_all += pairs * g_prof.reps;
+    g_prof.pairs_dense += pairs * g_prof.reps;
+    HIP_TRY(hipEventRecord(pp.a, r.s));
   }
+  for (int rep = 0; rep < (timed ? g_prof.reps : 1); ++rep) {
+    batch_tiles(r, v, mode);
+    HIP_TRY(hipGetLastError());
+  }
+  if (timed) HIP_TRY(hipEventRecord(pp.b, r.s));
   const int only_L = mode == kSoftLogLik;
   const int ncx = (only_L ? 1 : (bp.ncols_max + 63) / 64);
   hipLaunchKernelGGL(reduce_frames_kernel, dim3(bp.B, ncx), dim3(256), 0, r.s,
@@ -1375,24 +1541,31 @@ gmm_status batch_pass(BatchRun &r, int mode, int umode, double reg,
   return GMM_OK;
 }
 
+// theta_0: the one-hot M-step of the labels, or the caller's parameters.
+gmm_status batch_start(BatchRun &r, const int32_t *labels, const float *w, const float *mu,
+                       const float *cov, double reg) {
+  const BatchPlan &bp = *r.bp;
+  gmm_status st;
+  if (labels) {
+    if ((st = batch_pass(r, kLabels, kUpdMeanOnly, reg, nullptr, 1, 0)) != GMM_OK) return st;
+    return batch_pass(r, kLabels, kUpdFull, reg, nullptr, 1, 0);
+  }
+  const BFrame *frames = reinterpret_cast<const BFrame *>(at<unsigned char>(r.ws, bp.plan));
+  hipLaunchKernelGGL(precompute_frames_kernel, dim3(bp.B), dim3(kPreThreads), 0,
+                     r.s, w, mu, cov, frames, at<float>(r.ws, bp.cpar[r.cur]),
+                     at<float4>(r.ws, bp.shift[r.cur]), at<double>(r.ws, bp.th64),
+                     at<uint32_t>(r.ws, bp.status));
+  HIP_TRY(hipGetLastError());
+  return GMM_OK;
+}
+
 gmm_status enqueue_batched(BatchRun &r, const int32_t *labels, float *w,
                            float *mu, float *cov, double *loglik,
                            const gmm_fit_opts *opts) {
   gmm_status st;
   const int T = opts->iters, ll = T + 1;
   const double reg = opts->reg_covar;
-  const BatchPlan &bp = *r.bp;
-  const BFrame *frames = reinterpret_cast<const BFrame *>(at<unsigned char>(r.ws, bp.plan));
-  if (labels) {
-    if ((st = batch_pass(r, kLabels, kUpdMeanOnly, reg, nullptr, ll, 0)) != GMM_OK) return st;
-    if ((st = batch_pass(r, kLabels, kUpdFull, reg, nullptr, ll, 0)) != GMM_OK) return st;
-  } else {
-    hipLaunchKernelGGL(precompute_frames_kernel, dim3(bp.B), dim3(kPreThreads), 0,
-                       r.s, w, mu, cov, frames, at<float>(r.ws, bp.cpar[r.cur]),
-                       at<float4>(r.ws, bp.shift[r.cur]), at<double>(r.ws, bp.th64),
-                       at<uint32_t>(r.ws, bp.status));
-    HIP_TRY(hipGetLastError());
-  }
+  if ((st = batch_start(r, labels, w, mu, cov, reg)) != GMM_OK) return st;
   for (int t = 0; t < T; ++t) {
     if (opts->moment_mode == GMM_MOMENTS_TWO_PASS) {
       if ((st = batch_pass(r, kSoftStats, kUpdMeanOnly, reg, loglik, ll, t)) != GMM_OK) return st;
@@ -1402,6 +1575,58 @@ gmm_status enqueue_batched(BatchRun &r, const int32_t *labels, float *w,
     }
   }
   return batch_pass(r, kSoftLogLik, kUpdNone, reg, loglik, ll, T, w, mu, cov);
+}
+
+// Autotuning: from theta_0 (which no tile pass changes), one soft pass of
+// every shape in the plan, timed over 3 launches after a warm-up; the
+// fastest becomes the soft shape.
+gmm_status batch_autotune(BatchRun &r, BatchPlan &bp) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = -1;
+  float best_ms = 0.0f;
+  for (int i = 0; i < (int)bp.vars.size(); ++i) {
+    const BatchVariant &v = bp.vars[i];
+    batch_tiles(r, v, kSoftStats);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(e0, r.s));
+    for (int rep = 0; rep < 3; ++rep) batch_tiles(r, v, kSoftStats);
+    HIP_TRY(hipEventRecord(e1, r.s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (best < 0 || ms < best_ms) {
+      best = i;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  bp.soft_var = best;
+  btune_store(bp, bp.vars[best].spec);
+  return GMM_OK;
+}
+
+
+// The soft shape of a call: forced by GMM_BATCH_SHAPE, else the tuned one
+// (autotuning on), else the default; -2 when autotuning is on and this
+// batch has no tuned shape yet.
+int batch_soft_spec(const BatchPlan &bp) {
+  const char *e = getenv("GMM_BATCH_SHAPE");
+  if (e && *e && batch_spec_by_name(e) >= 0) return batch_spec_by_name(e);
+  if (autotune_on()) {
+    const int s = btune_lookup(bp);
+    return s >= 0 ? s : -2;
+  }
+  return batch_default_spec(bp.Kmax);
+}
+
+// Index of spec in the plan's shapes (the label shape when it is absent).
+int batch_var_index(const BatchPlan &bp, int spec) {
+  for (int i = 0; i < (int)bp.vars.size(); ++i)
+    if (bp.vars[i].spec == spec) return i;
+  return bp.lab_var;
 }
 
 }  // namespace
@@ -1492,7 +1717,7 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
   // that a captured graph records.
   if (graphs_enabled() && !guard.ptr && g_prof.reps == 0) {
     FitKey key{pts, init_labels, w, mu, cov, loglik, ws, n, ws_bytes,
-               opts->reg_covar, k, opts->iters, opts->moment_mode, 0,
+               opts->reg_covar, opts->tol, k, opts->iters, opts->moment_mode, 0,
                reinterpret_cast<const void *>(r.c.launch),
                r.cull ? reinterpret_cast<const void *>(r.cc.launch) : nullptr,
                sort_enabled()};
@@ -1585,6 +1810,10 @@ gmm_status gmm_loglik(const float *pts, int64_t n, const float *pose6,
   }
   if ((st = stage(r, pts, n, nullptr, Rt)) != GMM_OK) return st;
   if ((st = run_precompute(r, w, mu, cov)) != GMM_OK) return st;
+  if (g_prof.reps > 0) {
+    r.sink = &g_prof.pending;
+    r.time_loglik = true;
+  }
   return run_pass(r, kSoftLogLik, kUpdNone, 0.0, out_L, out_lse);
 }
 
@@ -1594,10 +1823,23 @@ size_t gmm_fit_batched_workspace_size(int32_t B, const int64_t *pt_off,
                                       const gmm_fit_opts *opts) {
   (void)opts;
   g_err[0] = 0;
-  if (!pt_off || !k_off) return 0;
+  if (!pt_off || !k_off || B <= 0 || pt_off[0] != 0 || k_off[0] != 0) return 0;
+  // sized for every launch shape the call may tune to or be forced to
   BatchPlan bp;
-  if (make_batch_plan(B, pt_off, k_off, &bp, batch_cull_wanted()) != GMM_OK) return 0;
+  if (make_batch_plan(B, pt_off, k_off, &bp, true) != GMM_OK) return 0;
   return bp.total;
+}
+
+const char *gmm_fit_batched_config(int32_t B, const int64_t *pt_off, const int32_t *k_off) {
+  g_err[0] = 0;
+  if (!pt_off || !k_off || B <= 0 || pt_off[0] != 0 || k_off[0] != 0) return "";
+  BatchPlan bp;
+  if (make_batch_plan(B, pt_off, k_off, &bp, false) != GMM_OK) return "";
+  const int s = batch_soft_spec(bp);
+  if (s < 0) return "";
+  // a shape that cannot run these frames falls back to the label shape
+  if (make_batch_plan(B, pt_off, k_off, &bp, false, s) != GMM_OK) return "";
+  return kBatchSpec[bp.vars[batch_var_index(bp, s)].spec].name;
 }
 
 gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
@@ -1614,61 +1856,96 @@ gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
   if (opts->moment_mode != GMM_MOMENTS_SHIFTED &&
       opts->moment_mode != GMM_MOMENTS_TWO_PASS)
     return fail(GMM_ERR_INVALID_ARG, "unknown moment_mode");
-  if (opts->flags & ~GMM_FLAG_ASYNC) return fail(GMM_ERR_INVALID_ARG, "unknown flags");
+  if (opts->flags & ~(GMM_FLAG_ASYNC | GMM_FLAG_DETERMINISTIC))
+    return fail(GMM_ERR_INVALID_ARG, "unknown flags");
+  if (opts->tol != 0.0) return fail(GMM_ERR_INVALID_ARG, "batched fits run a fixed T (tol = 0)");
+  if (B <= 0) return fail(GMM_ERR_INVALID_ARG, "B=%d must be positive", B);
   if (pt_off[0] != 0 || k_off[0] != 0)
     return fail(GMM_ERR_INVALID_ARG, "offsets must start at 0");
+  // the plan: every shape when tuning now, else the label shape and the soft shape
   BatchPlan bp;
-  gmm_status st = make_batch_plan(B, pt_off, k_off, &bp, batch_cull_wanted());
+  gmm_status st = make_batch_plan(B, pt_off, k_off, &bp, false);
   if (st != GMM_OK) return st;
+  int spec = batch_soft_spec(bp);
+  const bool tune = spec == -2;
+  if ((st = make_batch_plan(B, pt_off, k_off, &bp, tune, tune ? -1 : spec)) != GMM_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   WsGuard guard;
   if ((st = get_ws(&ws, &ws_bytes, bp.total, s, &guard)) != GMM_OK) return st;
-  // upload the plan (host buffer kept alive until the copy has completed)
-  std::vector<unsigned char> host(bp.plan_bytes, 0);
-  memcpy(host.data(), bp.frames.data(), sizeof(BFrame) * B);
-  for (const auto &c : bp.classes) {
-    memcpy(host.data() + c.seg_off, c.segs.data(), sizeof(BSeg) * c.segs.size());
-    memcpy(host.data() + c.blk_off, c.blk.data(), sizeof(int) * c.blk.size());
-  }
-  if (bp.cull) {
-    memcpy(host.data() + bp.cc.frames_off, bp.cc.frames.data(), sizeof(BFrame) * B);
-    memcpy(host.data() + bp.cc.seg_off, bp.cc.segs.data(), sizeof(BSeg) * bp.cc.segs.size());
-    memcpy(host.data() + bp.cc.blk_off, bp.cc.blk.data(), sizeof(int) * bp.cc.blk.size());
-  }
-  HIP_TRY(hipMemcpyAsync(at<unsigned char>(ws, bp.plan), host.data(),
-                         bp.plan_bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  hipLaunchKernelGGL(init_kernel, dim3(64), dim3(256), 0, s,
-                     at<uint32_t>(ws, bp.status), nullptr, 0,
-                     init_labels ? at<float4>(ws, bp.shift[0]) : nullptr, bp.Ktot);
-  HIP_TRY(hipGetLastError());
-  // stage every frame into its tiles (padded to kBatchCullT points)
-  const size_t stage_to = bp.sort ? bp.raw4 : bp.pts4;
-  for (int f = 0; f < B; ++f) {
-    const int64_t n = pt_off[f + 1] - pt_off[f];
-    const int64_t npad = ((n + kBatchCullT - 1) / kBatchCullT) * kBatchCullT;
-    hipLaunchKernelGGL(stage_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256),
-                       0, s, pts + 3 * pt_off[f], n, npad,
-                       init_labels ? init_labels + pt_off[f] : nullptr,
-                       bp.frames[f].K, nullptr,
-                       at<float4>(ws, stage_to) + bp.frames[f].toff * kBatchT,
-                       at<uint32_t>(ws, bp.status));
+  // plan upload (the host buffer lives until the copy has completed), status
+  // and shift reset, staging of every frame into its tiles (padded to
+  // kBatchCullT points), per-frame Morton order and tile spheres when the
+  // plan has a culled shape
+  auto prepare = [&]() -> gmm_status {
+    std::vector<unsigned char> host(bp.plan_bytes, 0);
+    memcpy(host.data(), bp.base.data(), sizeof(BFrame) * B);
+    for (const auto &v : bp.vars) {
+      memcpy(host.data() + v.frames_off, v.frames.data(), sizeof(BFrame) * B);
+      for (const auto &c : v.sets) {
+        memcpy(host.data() + c.seg_off, c.segs.data(), sizeof(BSeg) * c.segs.size());
+        memcpy(host.data() + c.blk_off, c.blk.data(), sizeof(int) * c.blk.size());
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(at<unsigned char>(ws, bp.plan), host.data(),
+                           bp.plan_bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    hipLaunchKernelGGL(init_kernel, dim3(64), dim3(256), 0, s,
+                       at<uint32_t>(ws, bp.status), nullptr, 0,
+                       init_labels ? at<float4>(ws, bp.shift[0]) : nullptr, bp.Ktot);
     HIP_TRY(hipGetLastError());
-  }
-  if (bp.sort && (st = batch_spatial_order(bp, ws, s)) != GMM_OK) return st;
-  if (bp.cull) {
-    const int64_t nt = bp.tiles * kBatchT / kBatchCullT;
-    hipLaunchKernelGGL(tile_sphere_kernel, dim3((unsigned)nt), dim3(256), 0, s,
-                       at<float4>(ws, bp.pts4), kBatchCullT, at<float4>(ws, bp.tsph));
-    HIP_TRY(hipGetLastError());
-  }
+    const size_t stage_to = bp.sort ? bp.raw4 : bp.pts4;
+    for (int f = 0; f < B; ++f) {
+      const int64_t n = pt_off[f + 1] - pt_off[f];
+      const int64_t npad = ((n + kBatchCullT - 1) / kBatchCullT) * kBatchCullT;
+      hipLaunchKernelGGL(stage_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256),
+                         0, s, pts + 3 * pt_off[f], n, npad,
+                         init_labels ? init_labels + pt_off[f] : nullptr,
+                         bp.base[f].K, nullptr,
+                         at<float4>(ws, stage_to) + bp.base[f].toff * kBatchT,
+                         at<uint32_t>(ws, bp.status));
+      HIP_TRY(hipGetLastError());
+    }
+    if (bp.sort) {
+      gmm_status so = batch_spatial_order(bp, ws, s);
+      if (so != GMM_OK) return so;
+      const int64_t nt = bp.tiles * kBatchT / kBatchCullT;
+      hipLaunchKernelGGL(tile_sphere_kernel, dim3((unsigned)nt), dim3(256), 0, s,
+                         at<float4>(ws, bp.pts4), kBatchCullT, at<float4>(ws, bp.tsph));
+      HIP_TRY(hipGetLastError());
+    }
+    return GMM_OK;
+  };
+  if ((st = prepare()) != GMM_OK) return st;
   BatchRun r;
-  r.bp = &bp;
   r.ws = ws;
   r.s = s;
-  // the iteration loop as one graph (direct launches when capture fails)
+  if (tune) {
+    // theta_0 and a few EM iterations with the label shape (the components
+    // of a k-means start are more compact than they stay, which favours
+    // culling), one timed soft pass per shape; then the plan of the winner
+    // alone, staged afresh, so that the fit equals one forced to that shape
+    r.bp = &bp;
+    if ((st = batch_start(r, init_labels, w, mu, cov, opts->reg_covar)) != GMM_OK) return st;
+    bp.soft_var = bp.lab_var;
+    for (int t = 0; t < std::min(opts->iters, kBatchTuneIters); ++t)
+      if ((st = batch_pass(r, kSoftStats, kUpdFull, opts->reg_covar, nullptr, 1, 0)) != GMM_OK)
+        return st;
+    if ((st = batch_autotune(r, bp)) != GMM_OK) return st;
+    spec = bp.vars[bp.soft_var].spec;
+    if ((st = make_batch_plan(B, pt_off, k_off, &bp, false, spec)) != GMM_OK) return st;
+    if ((st = prepare()) != GMM_OK) return st;
+    r.cur = 0;
+  }
+  bp.soft_var = batch_var_index(bp, spec);
+  r.bp = &bp;
+  debug_cfg("fit_batched", bp.Kmax, bp.tiles * kBatchT, kBatchSpec[bp.vars[bp.soft_var].spec].name,
+            (int)bp.vars[bp.soft_var].sets.size(), kBatchSpec[bp.vars[bp.soft_var].spec].block,
+            bp.vars[bp.soft_var].sets[0].lds);
+  // the iteration loop as one graph (direct launches when capture fails or
+  // when the tile kernels are being timed)
+  r.timed = g_prof.reps > 0;
   bool done = false;
-  if (graphs_enabled()) {
+  if (graphs_enabled() && !r.timed) {
     hipStream_t cs = capture_stream();
     hipEvent_t ev = nullptr;
     if (cs && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
@@ -1889,10 +2166,27 @@ gmm_status gmm_loglik_backward(const float *pts, int64_t n, const float *pose6,
   a.P = bc.P;
   a.mode = kSoftStats;
   a.ncols = r.L.ncols;
-  bc.launch(bc, r.s, at<float4>(ws, r.L.pts4), at<float>(ws, r.L.cpar[r.cur]),
-            at<float4>(ws, r.L.shift[r.cur]), Rt, grad_L,
-            at<double>(ws, r.L.part), g_pts, a, n);
-  HIP_TRY(hipGetLastError());
+  // profiling: the backward tile kernel is timed like the fit's E+M passes
+  // (it overwrites its per-point outputs and partial rows, so repeats
+  // change nothing)
+  EventPair pp;
+  const bool timed = g_prof.reps > 0;
+  if (timed) {
+    if (!make_pair(&pp)) return fail(GMM_ERR_DEVICE, "profiling event allocation failed");
+    pp.reps = g_prof.reps;
+    g_prof.pending.push_back(pp);
+    const int64_t all = (int64_t)g_prof.reps * a.ntiles * k;
+    g_prof.pairs_all += all;
+    g_prof.pairs_dense += all;
+    HIP_TRY(hipEventRecord(pp.a, r.s));
+  }
+  for (int rep = 0; rep < (timed ? g_prof.reps : 1); ++rep) {
+    bc.launch(bc, r.s, at<float4>(ws, r.L.pts4), at<float>(ws, r.L.cpar[r.cur]),
+              at<float4>(ws, r.L.shift[r.cur]), Rt, grad_L,
+              at<double>(ws, r.L.part), g_pts, a, n);
+    HIP_TRY(hipGetLastError());
+  }
+  if (timed) HIP_TRY(hipEventRecord(pp.b, r.s));
   const int ncx = (r.L.ncols + 63) / 64;
   hipLaunchKernelGGL(reduce_rows_kernel<256>, dim3(ncx, kRedChunks), dim3(256), 0,
                      r.s, at<double>(ws, r.L.part), bc.grid, r.L.ncols, 0,

@@ -1,0 +1,370 @@
+// MI355X (gfx950) 4D mixture (x, y, z, intensity): host side of the C ABI
+// calls gmm4_fit, gmm4_color_conditional and gmm4_joint_dist_sample
+// (include/gmm.h).  Kernels in em4_device.hpp.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "em4_device.hpp"
+#include "gmm.h"
+
+namespace gmm_host {
+extern thread_local char g_err[512];
+}
+
+namespace {
+
+using namespace gmm4_dev;
+using gmm_host::g_err;
+
+gmm_status fail(gmm_status s, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+#define HIP_TRY(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail(GMM_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_));   \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <typename T>
+T *at(void *ws, size_t off) {
+  return reinterpret_cast<T *>(static_cast<unsigned char *>(ws) + off);
+}
+
+int device_cus() {
+  static std::mutex mu;
+  static int cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if (cache[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      cache[dev] = v;
+  }
+  return cache[dev];
+}
+
+gmm_status status_from_bits(uint32_t bits) {
+  if (bits & kStBadArg) return fail(GMM_ERR_INVALID_ARG, "device: invalid label or parameter");
+  if (bits & kStNotSpd) return fail(GMM_ERR_NOT_SPD, "device: covariance not SPD");
+  if (bits & kStNonFinite) return fail(GMM_ERR_NONFINITE, "device: non-finite value");
+  return GMM_OK;
+}
+
+struct WsGuard {
+  void *ptr = nullptr;
+  hipStream_t s = nullptr;
+  ~WsGuard() {
+    if (ptr) (void)hipFreeAsync(ptr, s);
+  }
+};
+
+gmm_status get_ws(void **ws, size_t *ws_bytes, size_t need, hipStream_t s, WsGuard *g) {
+  if (*ws == nullptr) {
+    void *p = nullptr;
+    // GMM_FAULT_INJECT=oom: the allocation fails (tests of the error path)
+    const char *fi = getenv("GMM_FAULT_INJECT");
+    if (fi && strcmp(fi, "oom") == 0)
+      return fail(GMM_ERR_OOM, "hipMallocAsync(%zu) failed (GMM_FAULT_INJECT=oom)", need);
+    if (hipMallocAsync(&p, need, s) != hipSuccess)
+      return fail(GMM_ERR_OOM, "hipMallocAsync(%zu) failed", need);
+    g->ptr = p;
+    g->s = s;
+    *ws = p;
+    *ws_bytes = need;
+  }
+  if (*ws_bytes < need)
+    return fail(GMM_ERR_OOM, "workspace %zu bytes < %zu needed", *ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(*ws) & 255)
+    return fail(GMM_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  return GMM_OK;
+}
+
+// ----------------------------------------------------------------- fit
+struct Cfg4 {
+  int P = 0, trip = 0, grid = 0;
+  size_t lds = 0;
+  const void *kfn = nullptr;
+  void (*launch)(const Cfg4 &, hipStream_t, const float4 *, const int32_t *, const float *,
+                 const float4 *, double *, const Tile4Args &) = nullptr;
+};
+
+template <int TRIP>
+void launch_tile4(const Cfg4 &c, hipStream_t s, const float4 *pts, const int32_t *lab,
+                  const float *cpar, const float4 *shift, double *part, const Tile4Args &a) {
+  hipLaunchKernelGGL(em4_tile_kernel<TRIP>, dim3(c.grid), dim3(kBlock), c.lds, s, pts, lab,
+                     cpar, shift, part, a);
+}
+
+// Point subsets per component: the largest power of two P with P K <= the
+// block and P <= kT; TRIP = kT / P points each.
+bool make_cfg4(int K, int64_t n, Cfg4 *c) {
+  const int cus = device_cus();
+  if (cus <= 0 || K < 1 || K > kMaxK) return false;
+  int P = 1;
+  while (P * 2 <= kT && P * 2 * K <= kBlock) P *= 2;
+  c->P = P;
+  c->trip = kT / P;
+  switch (c->trip) {
+#define GMM4_TRIP(TR)                                                       \
+  case TR:                                                                  \
+    c->launch = &launch_tile4<TR>;                                          \
+    c->kfn = reinterpret_cast<const void *>(&em4_tile_kernel<TR>);          \
+    break;
+    GMM4_TRIP(1) GMM4_TRIP(2) GMM4_TRIP(4) GMM4_TRIP(8) GMM4_TRIP(16) GMM4_TRIP(32)
+    GMM4_TRIP(64)
+#undef GMM4_TRIP
+    default: return false;
+  }
+  c->lds = tile4_lds_bytes(K);
+  if (c->lds > 65536 && hipFuncSetAttribute(c->kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)c->lds) != hipSuccess)
+    return false;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c->kfn, kBlock, c->lds) !=
+          hipSuccess || per_cu <= 0)
+    return false;
+  const int64_t ntiles = (n + kT - 1) / kT;
+  c->grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, (int64_t)cus * per_cu));
+  return true;
+}
+
+struct Layout4 {
+  size_t status, cpar[2], shift[2], th64, red, part, total;
+  int ncols;
+};
+
+Layout4 layout4(int K, int grid) {
+  Layout4 L{};
+  size_t o = 0;
+  L.ncols = kNStat * K + 1;
+  L.status = o; o = align256(o + 256);
+  for (int i = 0; i < 2; ++i) {
+    L.cpar[i] = o; o = align256(o + (size_t)(K + 1) * kPar * sizeof(float));
+    L.shift[i] = o; o = align256(o + (size_t)K * sizeof(float4));
+  }
+  L.th64 = o; o = align256(o + (size_t)K * kTh * sizeof(double));
+  L.red = o; o = align256(o + (size_t)kRedChunks * L.ncols * sizeof(double));
+  L.part = o; o = align256(o + (size_t)grid * L.ncols * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+struct Run4 {
+  Cfg4 c;
+  Layout4 L;
+  void *ws = nullptr;
+  hipStream_t s = nullptr;
+  int K = 0, cur = 0;
+  int64_t n = 0;
+  const float4 *pts = nullptr;
+  const int32_t *labels = nullptr;
+};
+
+gmm_status pass4(Run4 &r, int mode, int umode, double reg, double *slot,
+                 float *ow = nullptr, float *omu = nullptr, float *ocov = nullptr) {
+  const Layout4 &L = r.L;
+  Tile4Args a;
+  a.n = r.n;
+  a.ntiles = (int)((r.n + kT - 1) / kT);
+  a.K = r.K;
+  a.P = r.c.P;
+  a.mode = mode;
+  a.ncols = L.ncols;
+  r.c.launch(r.c, r.s, r.pts, r.labels, at<float>(r.ws, L.cpar[r.cur]),
+             at<float4>(r.ws, L.shift[r.cur]), at<double>(r.ws, L.part), a);
+  HIP_TRY(hipGetLastError());
+  const int col0 = 0;
+  (void)col0;
+  hipLaunchKernelGGL(reduce4_kernel, dim3((L.ncols + 255) / 256, kRedChunks), dim3(256), 0,
+                     r.s, at<double>(r.ws, L.part), r.c.grid, L.ncols, at<double>(r.ws, L.red));
+  HIP_TRY(hipGetLastError());
+  const int nxt = 1 - r.cur;
+  Upd4Args ua;
+  ua.K = r.K;
+  ua.ncols = L.ncols;
+  ua.mode = mode;
+  ua.umode = umode;
+  ua.chunks = kRedChunks;
+  ua.reg = reg;
+  hipLaunchKernelGGL(update4_kernel, dim3(1), dim3(kUpdThreads), 0, r.s,
+                     at<double>(r.ws, L.red), at<float>(r.ws, L.cpar[r.cur]),
+                     at<float4>(r.ws, L.shift[r.cur]), at<float>(r.ws, L.cpar[nxt]),
+                     at<float4>(r.ws, L.shift[nxt]), at<double>(r.ws, L.th64), slot, ow, omu,
+                     ocov, at<uint32_t>(r.ws, L.status), ua);
+  HIP_TRY(hipGetLastError());
+  if (umode != kUpdNone) r.cur = nxt;
+  return GMM_OK;
+}
+
+gmm_status check_fit4(int64_t n, int32_t k) {
+  if (n <= 0 || n > GMM_MAX_N) return fail(GMM_ERR_INVALID_ARG, "n=%lld out of range", (long long)n);
+  if (k <= 0) return fail(GMM_ERR_INVALID_ARG, "k=%d must be positive", k);
+  if (k > kMaxK) return fail(GMM_ERR_UNSUPPORTED, "k=%d above the 4D limit %d", k, kMaxK);
+  if (k > n) return fail(GMM_ERR_INVALID_ARG, "k=%d > n=%lld", k, (long long)n);
+  return GMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gmm4_fit_workspace_size(int64_t n, int32_t k, const gmm_fit_opts *opts) {
+  (void)opts;
+  g_err[0] = 0;
+  if (check_fit4(n, k) != GMM_OK) return 0;
+  Cfg4 c;
+  if (!make_cfg4(k, n, &c)) return 0;
+  return layout4(k, c.grid).total;
+}
+
+gmm_status gmm4_fit(const float *pts, int64_t n, int32_t k, const int32_t *init_labels,
+                    float *w, float *mu, float *cov, double *loglik,
+                    const gmm_fit_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+  g_err[0] = 0;
+  gmm_status st = check_fit4(n, k);
+  if (st != GMM_OK) return st;
+  if (!pts || !w || !mu || !cov || !opts) return fail(GMM_ERR_INVALID_ARG, "NULL pointer argument");
+  if (reinterpret_cast<uintptr_t>(pts) & 15)
+    return fail(GMM_ERR_INVALID_ARG, "points must be 16-byte aligned (N x 4 float32)");
+  if (opts->iters < 0) return fail(GMM_ERR_INVALID_ARG, "iters < 0");
+  if (!(opts->reg_covar >= 0.0) || !isfinite(opts->reg_covar))
+    return fail(GMM_ERR_INVALID_ARG, "reg_covar must be finite and >= 0");
+  if (opts->moment_mode != GMM_MOMENTS_SHIFTED && opts->moment_mode != GMM_MOMENTS_TWO_PASS)
+    return fail(GMM_ERR_INVALID_ARG, "unknown moment_mode");
+  if (opts->flags & ~(GMM_FLAG_ASYNC | GMM_FLAG_DETERMINISTIC))
+    return fail(GMM_ERR_INVALID_ARG, "unknown flags");
+  if (opts->tol != 0.0) return fail(GMM_ERR_INVALID_ARG, "4D fits run a fixed T (tol = 0)");
+  Run4 r;
+  r.K = k;
+  r.n = n;
+  if (!make_cfg4(k, n, &r.c)) return fail(GMM_ERR_UNSUPPORTED, "no 4D launch configuration for k=%d", k);
+  r.L = layout4(k, r.c.grid);
+  r.s = static_cast<hipStream_t>(stream);
+  WsGuard guard;
+  if ((st = get_ws(&ws, &ws_bytes, r.L.total, r.s, &guard)) != GMM_OK) return st;
+  r.ws = ws;
+  r.pts = reinterpret_cast<const float4 *>(pts);
+  r.labels = init_labels;
+  hipLaunchKernelGGL(init4_kernel, dim3(1), dim3(256), 0, r.s, at<uint32_t>(ws, r.L.status),
+                     init_labels ? at<float4>(ws, r.L.shift[0]) : nullptr, k);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(check4_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, r.s,
+                     r.pts, init_labels, n, k, at<uint32_t>(ws, r.L.status));
+  HIP_TRY(hipGetLastError());
+  const double reg = opts->reg_covar;
+  if (init_labels) {
+    // theta_0 = M-step of the one-hot responsibilities: the mean (shift 0),
+    // then the scatter about it
+    if ((st = pass4(r, kLabels, kUpdMeanOnly, reg, nullptr)) != GMM_OK) return st;
+    if ((st = pass4(r, kLabels, kUpdFull, reg, nullptr)) != GMM_OK) return st;
+  } else {
+    hipLaunchKernelGGL(precompute4_kernel, dim3(1), dim3(kUpdThreads), 0, r.s, w, mu, cov, k,
+                       at<float>(ws, r.L.cpar[0]), at<float4>(ws, r.L.shift[0]),
+                       at<double>(ws, r.L.th64), at<uint32_t>(ws, r.L.status));
+    HIP_TRY(hipGetLastError());
+  }
+  for (int t = 0; t < opts->iters; ++t) {
+    double *slot = loglik ? loglik + t : nullptr;
+    if (opts->moment_mode == GMM_MOMENTS_TWO_PASS) {
+      if ((st = pass4(r, kSoftStats, kUpdMeanOnly, reg, slot)) != GMM_OK) return st;
+      slot = nullptr;
+    }
+    if ((st = pass4(r, kSoftStats, kUpdFull, reg, slot)) != GMM_OK) return st;
+  }
+  if ((st = pass4(r, kSoftLogLik, kUpdNone, reg, loglik ? loglik + opts->iters : nullptr, w, mu,
+                  cov)) != GMM_OK)
+    return st;
+  if (opts->flags & GMM_FLAG_ASYNC) return GMM_OK;
+  uint32_t bits = 0;
+  HIP_TRY(hipMemcpyAsync(&bits, at<uint32_t>(ws, r.L.status), sizeof bits,
+                         hipMemcpyDeviceToHost, r.s));
+  HIP_TRY(hipStreamSynchronize(r.s));
+  return status_from_bits(bits);
+}
+
+size_t gmm4_color_conditional_workspace_size(int32_t k) {
+  g_err[0] = 0;
+  if (k <= 0 || k > kMaxK) return 0;
+  return align256(256) + align256((size_t)k * kCond * sizeof(float));
+}
+
+gmm_status gmm4_color_conditional(const float *locs, int64_t m, int32_t k, const float *w,
+                                  const float *mu, const float *cov, float *expected,
+                                  float *variance, void *ws, size_t ws_bytes, void *stream) {
+  g_err[0] = 0;
+  if (m <= 0 || m > GMM_MAX_N) return fail(GMM_ERR_INVALID_ARG, "m=%lld out of range", (long long)m);
+  if (k <= 0) return fail(GMM_ERR_INVALID_ARG, "k=%d must be positive", k);
+  if (k > kMaxK) return fail(GMM_ERR_UNSUPPORTED, "k=%d above the 4D limit %d", k, kMaxK);
+  if (!locs || !w || !mu || !cov || !expected || !variance)
+    return fail(GMM_ERR_INVALID_ARG, "NULL pointer argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  WsGuard guard;
+  gmm_status st = get_ws(&ws, &ws_bytes, gmm4_color_conditional_workspace_size(k), s, &guard);
+  if (st != GMM_OK) return st;
+  uint32_t *status = at<uint32_t>(ws, 0);
+  float *cb = at<float>(ws, align256(256));
+  hipLaunchKernelGGL(init4_kernel, dim3(1), dim3(64), 0, s, status, nullptr, 0);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(cond_prep_kernel, dim3(1), dim3(kUpdThreads), 0, s, w, mu, cov, k, cb,
+                     status);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(cond4_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, locs, m,
+                     cb, k, expected, variance, status);
+  HIP_TRY(hipGetLastError());
+  return GMM_OK;
+}
+
+size_t gmm4_joint_dist_sample_workspace_size(int32_t k) {
+  g_err[0] = 0;
+  if (k <= 0 || k > GMM_MAX_K) return 0;
+  return align256(256) + align256((size_t)k * sizeof(double)) +
+         align256((size_t)k * 10 * sizeof(double)) + align256(sizeof(int));
+}
+
+gmm_status gmm4_joint_dist_sample(int32_t k, const float *w, const float *mu, const float *cov,
+                                  int64_t m, const double *u, const float *z, float *out,
+                                  int32_t *comp, void *ws, size_t ws_bytes, void *stream) {
+  g_err[0] = 0;
+  if (m <= 0 || m > GMM_MAX_N) return fail(GMM_ERR_INVALID_ARG, "m=%lld out of range", (long long)m);
+  if (k <= 0) return fail(GMM_ERR_INVALID_ARG, "k=%d must be positive", k);
+  if (k > GMM_MAX_K) return fail(GMM_ERR_UNSUPPORTED, "k=%d above GMM_MAX_K", k);
+  if (!w || !mu || !cov || !u || !z || !out) return fail(GMM_ERR_INVALID_ARG, "NULL pointer argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  WsGuard guard;
+  gmm_status st = get_ws(&ws, &ws_bytes, gmm4_joint_dist_sample_workspace_size(k), s, &guard);
+  if (st != GMM_OK) return st;
+  size_t o = 0;
+  uint32_t *status = at<uint32_t>(ws, o); o = align256(o + 256);
+  double *run = at<double>(ws, o); o = align256(o + (size_t)k * sizeof(double));
+  double *Lf = at<double>(ws, o); o = align256(o + (size_t)k * 10 * sizeof(double));
+  int *last = at<int>(ws, o);
+  hipLaunchKernelGGL(init4_kernel, dim3(1), dim3(64), 0, s, status, nullptr, 0);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(sample_prep_kernel, dim3(1), dim3(256), 0, s, w, cov, k, run, Lf, last,
+                     status);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(sample4_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, run, Lf,
+                     last, mu, k, m, u, z, out, comp, status);
+  HIP_TRY(hipGetLastError());
+  return GMM_OK;
+}
+
+}  // extern "C"

@@ -21,7 +21,8 @@ def rel(a, b):
 
 
 def rms_radius(X):
-    X = np.asarray(X, np.float64).reshape(-1, 3)
+    X = np.asarray(X, np.float64)
+    X = X.reshape(X.shape[0], -1)
     return float(np.sqrt(((X - X.mean(axis=0)) ** 2).sum(axis=1).mean()))
 
 
@@ -31,8 +32,9 @@ def per_component(got, ref, X, pi_min=PI_MIN):
     w, mu, cov = (np.asarray(a, np.float64) for a in got)
     wr, mur, covr = (np.asarray(a, np.float64) for a in ref)
     K = wr.shape[0]
-    mu, mur = mu.reshape(K, 3), mur.reshape(K, 3)
-    cov, covr = cov.reshape(K, 3, 3), covr.reshape(K, 3, 3)
+    D = mur.size // K
+    mu, mur = mu.reshape(K, D), mur.reshape(K, D)
+    cov, covr = cov.reshape(K, D, D), covr.reshape(K, D, D)
     sel = wr >= pi_min
     if not sel.any():
         return {"pi_b": 0.0, "mu_b": 0.0, "cov_b": 0.0}
@@ -40,8 +42,8 @@ def per_component(got, ref, X, pi_min=PI_MIN):
     e_pi = np.abs(w - wr)[sel] / wr[sel]
     e_mu = (np.linalg.norm(mu - mur, axis=1) /
             (np.linalg.norm(mur, axis=1) + R))[sel]
-    e_cov = (np.linalg.norm((cov - covr).reshape(K, 9), axis=1) /
-             np.linalg.norm(covr.reshape(K, 9), axis=1))[sel]
+    e_cov = (np.linalg.norm((cov - covr).reshape(K, D * D), axis=1) /
+             np.linalg.norm(covr.reshape(K, D * D), axis=1))[sel]
     return {"pi_b": float(e_pi.max()), "mu_b": float(e_mu.max()),
             "cov_b": float(e_cov.max())}
 

@@ -202,3 +202,73 @@ def test_batched_full_size_bench_workload():
         err = np.abs(Lb - Lr) / np.maximum(np.abs(Lr), X.shape[0])
         print("frame", i, X.shape[0], k, err.max(), flush=True)
         assert err.max() <= 1e-4
+
+
+BATCH_SHAPES = ["bb512", "bb1024", "bc512p8s32", "bc512p8s64", "bc512p16s64"]
+
+
+@pytest.mark.parametrize("shape", BATCH_SHAPES)
+def test_every_batch_shape_one_step_parity(shape, monkeypatch):
+    """Each soft-pass shape the batched autotuner may pick meets the
+    one-step bar on every frame (per array and per component)."""
+    from paper_2307_00071_amd import _lib
+    monkeypatch.setenv("GMM_BATCH_SHAPE", shape)
+    frames = _frames(5, 1400, 2000, 30000, 5, 220)
+    ns, ks = [X.shape[0] for X, _ in frames], [k for _, k in frames]
+    if _lib.batch_config(ns, ks) != shape:
+        pytest.skip("shape %s cannot run these frames" % shape)
+    print("case: batched shape %s" % shape, flush=True)
+    thetas = []
+    for X, k in frames:
+        lab = synth.kmeanspp_labels(X, k, 9)
+        thetas.append(tuple(a.astype(np.float32)
+                            for a in oracle.fit(X, k, 1e-3, 2, labels=lab)[:3]))
+    res = gmm.fit_batched([_to(X) for X, _ in frames], ks, iters=1,
+                          theta0_list=[tuple(_to(a) for a in th) for th in thetas])
+    torch.cuda.synchronize()
+    for (X, k), th, r in zip(frames, thetas, res):
+        wr, mur, covr, L0 = oracle.em_step(X, *(a.astype(np.float64) for a in th), 1e-3)
+        e = _one_step_errors(r, X, (wr, mur, covr))
+        assert max(e.values()) <= 1e-5, (shape, k, e)
+        assert abs(r.loglik[0].item() - L0) <= 1e-5 * max(abs(L0), X.shape[0])
+
+
+def test_batch_autotune_picks_caches_and_keeps_parity(monkeypatch, tmp_path):
+    """With autotuning on, the first batched fit times every shape and keeps
+    the fastest: the cache file names it, the library reports it, and the
+    fit meets the final-L bar against the oracle; a second call reuses the
+    tuned shape and agrees with a call forced to that shape bit for bit."""
+    from paper_2307_00071_amd import _lib
+    print("case: batched autotune", flush=True)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("GMM_AUTOTUNE_CACHE", str(cache))
+    frames = _frames(6, 1500, 5000, 40000, 10, 150)
+    ns, ks = [X.shape[0] for X, _ in frames], [k for _, k in frames]
+    labs = [synth.kmeanspp_labels(X, k, 2) for X, k in frames]
+    args = ([_to(X) for X, _ in frames], ks)
+    lab_t = [_to(l, torch.int32) for l in labs]
+    _lib.set_autotune(True)
+    try:
+        assert _lib.batch_config(ns, ks) == ""
+        T = 8
+        a = gmm.fit_batched(*args, iters=T, labels_list=lab_t)
+        torch.cuda.synchronize()
+        shape = _lib.batch_config(ns, ks)
+        assert shape in BATCH_SHAPES, shape
+        line = [l for l in cache.read_text().splitlines() if l.startswith("batch")][-1]
+        assert line.split()[-1] == shape
+        b = gmm.fit_batched(*args, iters=T, labels_list=lab_t)
+        torch.cuda.synchronize()
+    finally:
+        _lib.set_autotune(False)
+    monkeypatch.setenv("GMM_BATCH_SHAPE", shape)
+    c = gmm.fit_batched(*args, iters=T, labels_list=lab_t)
+    torch.cuda.synchronize()
+    for ra, rb, rc in zip(a, b, c):
+        for u, v, x in zip(ra, rb, rc):
+            np.testing.assert_array_equal(u.cpu().numpy(), v.cpu().numpy())
+            np.testing.assert_array_equal(u.cpu().numpy(), x.cpu().numpy())
+    for (X, k), lab, r in zip(frames, labs, a):
+        Lr = oracle.fit(X, k, 1e-3, T, labels=lab)[3]
+        L = r.loglik.cpu().numpy()
+        assert np.abs(L - Lr).max() <= 1e-4 * max(np.abs(Lr).max(), X.shape[0])

@@ -528,3 +528,60 @@ def test_collapsed_component_of_identical_points(mode):
     assert max(errs.values()) <= 1e-5, errs
     np.testing.assert_array_equal(got[1][8], p0[0])
     np.testing.assert_allclose(got[2][8], 1e-3 * np.eye(3), rtol=0, atol=1e-9)
+
+
+def test_fault_injected_allocation_failure(monkeypatch):
+    """GMM_FAULT_INJECT=oom: a call without a workspace reports OOM (nothing
+    enqueued); the same call then succeeds once the fault is lifted."""
+    import ctypes
+    _case("fault injection oom")
+    lib = _lib.load()
+    X = _depth_subset(5000, seed=13)
+    lab = synth.kmeanspp_labels(X, 8, 1)
+    pts, labt = _to(X), _to(lab, torch.int32)
+    w = torch.empty(8, device=DEV)
+    mu = torch.empty(8, 3, device=DEV)
+    cov = torch.empty(8, 3, 3, device=DEV)
+    opts = _lib.FitOpts(3, 1e-3, 0, 0)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    args = (p(pts), X.shape[0], 8, p(labt), p(w), p(mu), p(cov), None, ctypes.byref(opts),
+            None, 0, ctypes.c_void_p(torch.cuda.current_stream(DEV).cuda_stream))
+    monkeypatch.setenv("GMM_FAULT_INJECT", "oom")
+    assert lib.gmm_fit(*args) == 4
+    assert b"GMM_FAULT_INJECT" in lib.gmm_last_error()
+    monkeypatch.delenv("GMM_FAULT_INJECT")
+    assert lib.gmm_fit(*args) == 0
+    wr, mur, covr, _ = oracle.fit(X, 8, 1e-3, 3, labels=lab)
+    assert _rel(mu.cpu().numpy(), mur) <= 1e-5
+
+
+@pytest.mark.parametrize("mode", ["shifted", "two_pass"])
+def test_tolerance_stops_early_like_a_shorter_fit(mode):
+    """tol > 0: after the M-step of the first iteration t >= 1 with
+    |L(theta_t) - L(theta_t-1)| <= tol N the fit keeps theta_t+1 and skips
+    the rest on the device: its outputs equal a fixed (t + 1)-iteration
+    fit bit for bit, the skipped L entries are NaN, and the last entry is
+    L(theta_t+1)."""
+    _case("tolerance " + mode)
+    X = _blob_case(7)
+    N, K, T, tol = X.shape[0], 8, 40, 2e-5
+    lab = synth.kmeanspp_labels(X, K, 1)
+    Lf = _fit(X, K, T, labels=lab, mode=mode)[3]
+    d = np.abs(np.diff(Lf[:T]))
+    hit = np.flatnonzero(d <= tol * N)
+    assert hit.size, "the fit never meets the tolerance"
+    t_star = int(hit[0]) + 1
+    assert t_star + 1 < T
+    r = gmm.fit(_to(X), K, iters=T, reg_covar=1e-3, labels=_to(lab, torch.int32),
+                moment_mode=mode, tol=tol)
+    torch.cuda.synchronize()
+    L = r.loglik.cpu().numpy()
+    np.testing.assert_array_equal(L[:t_star + 1], Lf[:t_star + 1])
+    assert np.isnan(L[t_star + 1:T]).all()
+    w, mu, cov, Ls = _fit(X, K, t_star + 1, labels=lab, mode=mode)
+    np.testing.assert_array_equal(r.weights.cpu().numpy(), w.astype(np.float32))
+    np.testing.assert_array_equal(r.means.cpu().numpy(), mu.astype(np.float32))
+    np.testing.assert_array_equal(r.covariances.cpu().numpy(), cov.astype(np.float32))
+    assert L[T] == Ls[t_star + 1]
+    with pytest.raises(_lib.GmmError):
+        gmm.fit(_to(X), K, iters=3, labels=_to(lab, torch.int32), tol=-1.0)

@@ -15,7 +15,11 @@ measure the cancellation, not the arithmetic):
     largest entry;
 with N_b = g_w[b] w_b.  The bar is |gpu - oracle| <= 1e-5 scale + 1e-4 |oracle|
 for the component sums and the pose (FP64 sums of FP32 terms whose relative
-rounding is a few 1e-7), and 1e-4 (scale + |oracle|) for the per-point
+rounding is a few 1e-7), plus a floor of 1e-7 of the array's largest scale
+(1e-6 for g_w): a component holding a vanishing share of the points is
+built from far-tail responsibilities, whose FP32 exponentials lose relative
+precision and flush to zero below 2^-126 while the oracle keeps them; and
+1e-4 (scale + |oracle|) for the per-point
 gradients (one FP32 evaluation each: the transformed point y = R x + t is
 rounded to FP32, an absolute error near 1e-6 m that is ~3e-5 of a 3 cm
 standard deviation).  L must agree to 1e-5 relative (floor N).
@@ -87,11 +91,11 @@ def _elementwise(g, gr, th64, keys):
         a = np.asarray(g[key], np.float64)
         r = gr[key]
         if key == "w":
-            bar = 1e-5 * sc["w"] + 1e-30
+            bar = 1e-5 * sc["w"] + 1e-6 * sc["w"].max() + 1e-30
         elif key == "pts":
             bar = 1e-4 * (sc["pts"] + np.abs(r)) + 1e-30
         else:
-            bar = 1e-5 * sc[key] + 1e-4 * np.abs(r) + 1e-30
+            bar = 1e-5 * sc[key] + 1e-4 * np.abs(r) + 1e-7 * sc[key].max() + 1e-30
         out[key] = float((np.abs(a - r) / bar).max())
     return out
 
@@ -105,7 +109,7 @@ def _check(src, pose, th):
     L = gmm.loglik(_to(src), *(_to(a) for a in th), pose6=tpose)
     g = gmm.loglik_backward(_to(src), *(_to(a) for a in th), pose6=tpose)
     torch.cuda.synchronize()
-    g = {k: v.cpu().numpy() for k, v in g.items()}
+    g = {k: v.cpu().numpy() for k, v in g.items() if v is not None}
     N = src.shape[0]
     keys = ("pts", "w", "mu", "cov") + (("pose",) if pose is not None else ())
     errs = {"L": abs(L.item() - Lr) / max(abs(Lr), N)}
