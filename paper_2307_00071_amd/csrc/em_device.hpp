@@ -52,8 +52,12 @@ enum UpdMode { kUpdFull = 0, kUpdMeanOnly = 1, kUpdNone = 2 };
 //   [0..2] mu  [3] (c_b - C) * log2(e)  [4..9] s * P (P00 P10 P11 P20 P21 P22)
 //   [10] an upper bound of the Frobenius norm of s * P (tile culling)
 // with s = sqrt(log2(e) / 2), c_b = ln pi_b - 3/2 ln 2pi + sum_j ln P_jj
-// (eq. 3) and C = max_b c_b, so [3] - |P' (x - mu)|^2 = log2(e)(l_nb - C) <= 0.
-// After the K blocks: C * log2(e) as a double.
+// (eq. 3) and a bound C >= max_b c_b, so [3] - |P' (x - mu)|^2 =
+// log2(e)(l_nb - C) <= 0.  After the K blocks: C * log2(e) as a double.
+// C is max_b c_b for caller parameters and lambda = 0, and the static bound
+// 3/2 ln(1 / lambda) - 3/2 ln 2pi for parameters from an M-step with
+// lambda > 0 (every eigenvalue of such a Sigma_b is at least lambda, so
+// prod_j P_jj <= lambda^-3/2, and pi_b <= 1).
 // Shift array: the FP32 point the M-phase subtracts, per component.
 // FP64 state ("th64"), per component (16 doubles):
 //   [0] pi  [1..3] mu  [4..9] Sigma lower (00 10 11 20 21 22)  [10] N_b
@@ -552,6 +556,11 @@ struct TileArgs {
   unsigned long long *pairs = nullptr;
   // fits with a tolerance: bit 0 set = converged, the pass does nothing
   const unsigned *conv = nullptr;
+  // order of a partial row: 0 = statistic-major (statistic j of component
+  // b at j K + b); 1 = component-major (at b kNStat + j: a component's ten
+  // sums adjacent), read by the fused reduction + M-step.  The
+  // log-likelihood sum is last either way.
+  int cmaj = 0;
 };
 
 #ifndef GMM_TILE_WPE
@@ -721,7 +730,7 @@ __attribute__((amdgpu_waves_per_eu(GMM_TILE_WPE, 8))) void em_tile_kernel(
           if (b < K) {
             double sum = 0.0;
             for (int qq = 0; qq < P; ++qq) sum += D[qq * KC + i];
-            row[j * K + b] = sum;
+            row[a.cmaj ? b * kNStat + j : j * K + b] = sum;
           }
         }
       }
@@ -1293,14 +1302,19 @@ __device__ __forceinline__ void cull_tiles(
 }
 
 // The FP64 sums and the lse sum of one frame into its partial row.
+// cmaj: the row in component-major order (the LDS order of the sums).
 template <int BLOCK>
 __device__ __forceinline__ void cull_end(const CullLds &L, double *__restrict__ row,
-                                         int K, int mode, double Lacc) {
+                                         int K, int mode, double Lacc, bool cmaj = false) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (mode != kSoftLogLik) {
-    for (int i = tid; i < K * kNStat; i += BLOCK) {
-      const int j = i / K, b = i - j * K;
-      row[i] = L.acc[(size_t)b * kNStat + j];
+    if (cmaj) {
+      for (int i = tid; i < K * kNStat; i += BLOCK) row[i] = L.acc[i];
+    } else {
+      for (int i = tid; i < K * kNStat; i += BLOCK) {
+        const int j = i / K, b = i - j * K;
+        row[i] = L.acc[(size_t)b * kNStat + j];
+      }
     }
   }
   double v = Lacc;
@@ -1340,7 +1354,7 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
   cull_tiles<BLOCK, T, TRIP, SCAP, CPR, LAB, MEANS>(L, pts, sph, cpar, shift, a.K, a.mode,
                                                    blockIdx.x, a.ntiles, gridDim.x, lse_out,
                                                    Lacc, npairs);
-  cull_end<BLOCK>(L, part + (size_t)blockIdx.x * a.ncols, a.K, a.mode, Lacc);
+  cull_end<BLOCK>(L, part + (size_t)blockIdx.x * a.ncols, a.K, a.mode, Lacc, a.cmaj != 0);
   if (threadIdx.x == 0 && a.pairs) atomicAdd(a.pairs, npairs);
 }
 
@@ -1412,9 +1426,13 @@ struct UpdPtrs {
   double *loglik_slot;
   float *out_w, *out_mu, *out_cov;
   uint32_t *status;
-  // fits with a tolerance: [0] bit 0 converged, bit 1 L_prev valid; the
-  // double at [2] holds L_prev.  NULL otherwise.
+  // fits with a tolerance: *conv is this pass's state (bit 0 converged,
+  // bit 1 L_prev valid), read by every block; a full M-step writes the next
+  // pass's state to *conv_next (a different word, so no block of the same
+  // launch can see it) and L_prev to *Lprev.  NULL otherwise.
   unsigned *conv = nullptr;
+  unsigned *conv_next = nullptr;
+  double *Lprev = nullptr;
 };
 
 // tot = the column sums of red2 (LDS), the log-likelihood slot, then the
@@ -1427,6 +1445,7 @@ __device__ __forceinline__ void update_body(const UpdPtrs &q, const UpdArgs &a,
     // converged: the iterations left are not run (their L is NaN); the
     // parameters carry over to the set the next pass reads
     if (tid == 0 && q.loglik_slot) q.loglik_slot[0] = (double)NAN;
+    if (tid == 0 && q.conv_next) *q.conv_next = *q.conv;
     if (a.umode != kUpdNone) {
       for (int i = tid; i < (K + 1) * kParStride; i += kUpdThreads) q.cpar_out[i] = q.cpar_in[i];
       for (int b = tid; b < K; b += kUpdThreads) q.shift_out[b] = q.shift_in[b];
@@ -1466,13 +1485,12 @@ __device__ __forceinline__ void update_body(const UpdPtrs &q, const UpdArgs &a,
                                  q.status);
     // stopping rule, after a full M-step: theta_(t+1) is kept and the
     // following iterations are skipped once L changed by at most tol_abs
-    if (tid == 0 && q.conv && a.umode == kUpdFull && a.mode == kSoftStats) {
+    if (tid == 0 && q.conv_next && a.umode == kUpdFull && a.mode == kSoftStats) {
       const double L = tot[kNStat * K];
-      double *Lprev = reinterpret_cast<double *>(q.conv + 2);
       unsigned f = *q.conv;
-      if ((f & 2u) && fabs(L - *Lprev) <= a.tol_abs) f |= 1u;
-      *Lprev = L;
-      *q.conv = f | 2u;
+      if ((f & 2u) && fabs(L - *q.Lprev) <= a.tol_abs) f |= 1u;
+      *q.Lprev = L;
+      *q.conv_next = f | 2u;
     }
   } else if (q.out_w) {
     for (int b = tid; b < K; b += kUpdThreads) {
@@ -1486,6 +1504,179 @@ __device__ __forceinline__ void update_body(const UpdPtrs &q, const UpdArgs &a,
       cv[2] = cv[6] = (float)t[7];
       cv[5] = cv[7] = (float)t[8];
       cv[8] = (float)t[9];
+    }
+  }
+}
+
+// ------------------------------------------- fused reduction and M-step
+// For lambda > 0 the M-step of a component needs no other component: the
+// bound C is the static one above, and sum_a N_a is n + K eps_N (each
+// point's responsibilities sum to one).  The tile pass then writes its
+// partial rows component-major (a component's ten sums adjacent), and one
+// block per component sums its ten columns over the rows and updates it in
+// FP64: thread (g, s) takes statistic s of the rows g, g + G, g + 2G, ...
+// (G = kFuseGroups, added in row order), the G group sums are added by a
+// fixed pairwise tree; block 0's last wave also sums the log-likelihood
+// column (lane l the rows l, l + 64, ..., then a fixed butterfly).  One
+// launch instead of reduce_rows_kernel + update_kernel, bitwise
+// reproducible.
+constexpr int kFuseGroups = 64;
+constexpr int kFuseThreads = kNStat * kFuseGroups + 64;   // then one wave for L
+
+struct FuseArgs {
+  int K, ncols, nrows, mode, umode;
+  double reg;
+  double lnZ;      // ln(n + K eps_N) - 3/2 ln(lambda): c_b - C = ln(N_b P00 P11 P22) - lnZ
+  double Ntot;     // n + K eps_N
+  double Chdr;     // C log2(e)
+  double tol_abs;  // as UpdArgs
+};
+
+__global__ __launch_bounds__(kFuseThreads) void reduce_update_kernel(
+    const double *__restrict__ part, UpdPtrs q, FuseArgs a) {
+  __shared__ double sums[kFuseGroups * kNStat];
+  __shared__ double tot[kNStat + 1];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int K = a.K;
+  const int b = blockIdx.x;
+  if (q.conv && (*q.conv & 1u)) {
+    // converged: nothing runs; the parameters carry over, L is NaN
+    if (b == 0 && tid == 0 && q.loglik_slot) q.loglik_slot[0] = (double)NAN;
+    if (b == 0 && tid == 0 && q.conv_next) *q.conv_next = *q.conv;
+    if (a.umode != kUpdNone) {
+      if (tid < kParStride)
+        q.cpar_out[(size_t)b * kParStride + tid] = q.cpar_in[(size_t)b * kParStride + tid];
+      if (tid == 0) q.shift_out[b] = q.shift_in[b];
+      if (b == 0 && tid == 0)
+        *reinterpret_cast<double *>(q.cpar_out + (size_t)K * kParStride) =
+            *reinterpret_cast<const double *>(q.cpar_in + (size_t)K * kParStride);
+    }
+    return;
+  }
+  const bool lcol = b == 0 && a.mode != kLabels;
+  const bool stats = a.mode != kSoftLogLik;
+  constexpr int NS = kNStat * kFuseGroups;
+  if (tid < NS) {
+    if (stats) {
+      const int g = tid / kNStat, st = tid - g * kNStat;
+      const double *src = part + (size_t)b * kNStat + st;
+      constexpr int G = kFuseGroups;
+      // rounds of 16 rows, every load in flight (rows past the end add 0)
+      double acc = 0.0;
+      for (int r = g; r < a.nrows; r += 16 * G) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          v[u] = (r + u * G < a.nrows) ? src[(size_t)(r + u * G) * a.ncols] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += v[u];
+      }
+      sums[tid] = acc;
+    }
+  } else if (lcol) {
+    const double *src = part + (size_t)kNStat * K;
+    double acc = 0.0;
+    for (int r = lane; r < a.nrows; r += 16 * 64) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        v[u] = (r + u * 64 < a.nrows) ? src[(size_t)(r + u * 64) * a.ncols] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += v[u];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) tot[kNStat] = acc;
+  }
+  // group g += group g + half for every statistic, half = G/2, ..., 1
+#pragma unroll
+  for (int half = kFuseGroups / 2; half > 0; half >>= 1) {
+    __syncthreads();
+    if (stats && tid < half * kNStat) sums[tid] += sums[tid + half * kNStat];
+  }
+  if (stats && tid < kNStat) tot[tid] = sums[tid];
+  __syncthreads();
+  if (lcol && tid == 0 && q.loglik_slot) {
+    const double L = tot[kNStat];
+    q.loglik_slot[0] = L;
+    if (!isfinite(L)) set_status(q.status, kStNonFinite);
+  }
+  if (tid != 0) return;
+  if (a.umode == kUpdNone) {
+    if (q.out_w) {
+      const double *t = q.th64 + (size_t)b * kTh64Stride;
+      q.out_w[b] = (float)t[0];
+      for (int j = 0; j < 3; ++j) q.out_mu[3 * b + j] = (float)t[1 + j];
+      float *cv = q.out_cov + 9 * b;
+      cv[0] = (float)t[4];
+      cv[1] = cv[3] = (float)t[5];
+      cv[4] = (float)t[6];
+      cv[2] = cv[6] = (float)t[7];
+      cv[5] = cv[7] = (float)t[8];
+      cv[8] = (float)t[9];
+    }
+    return;
+  }
+  const double N0 = tot[0];
+  const double S1[3] = {tot[1], tot[2], tot[3]};
+  const float4 mf = q.shift_in[b];
+  const double m[3] = {mf.x, mf.y, mf.z};
+  const double Nb = N0 + kEpsN;
+  const double rN = 1.0 / Nb;
+  double mu[3], dl[3];
+  for (int j = 0; j < 3; ++j) {
+    mu[j] = (S1[j] + N0 * m[j]) * rN;
+    dl[j] = mu[j] - m[j];
+  }
+  bool fin = isfinite(N0) && isfinite(S1[0]) && isfinite(S1[1]) && isfinite(S1[2]);
+  if (a.umode == kUpdMeanOnly) {
+    if (!fin) set_status(q.status, kStNonFinite);
+    q.shift_out[b] = make_float4((float)mu[0], (float)mu[1], (float)mu[2], 0.0f);
+    for (int j = 0; j < kParStride; ++j)
+      q.cpar_out[(size_t)b * kParStride + j] = q.cpar_in[(size_t)b * kParStride + j];
+    if (b == 0)
+      *reinterpret_cast<double *>(q.cpar_out + (size_t)K * kParStride) =
+          *reinterpret_cast<const double *>(q.cpar_in + (size_t)K * kParStride);
+    return;
+  }
+  const int ij[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
+  double C[6];
+  for (int j = 0; j < 6; ++j) {
+    const int r = ij[j][0], c = ij[j][1];
+    const double s2 = tot[4 + j];
+    const double v = s2 - S1[r] * dl[c] - dl[r] * S1[c] + N0 * dl[r] * dl[c];
+    C[j] = v * rN + ((r == c) ? a.reg : 0.0);
+    fin = fin && isfinite(s2);
+  }
+  if (!fin) set_status(q.status, kStNonFinite);
+  double P[6];
+  double cb = -INFINITY;
+  if (chol_inv3(C, P)) cb = log(Nb * P[0] * P[2] * P[5]);
+  if (!isfinite(cb)) set_status(q.status, kStNotSpd);
+  double *t = q.th64 + (size_t)b * kTh64Stride;
+  t[0] = Nb / a.Ntot;
+  for (int j = 0; j < 3; ++j) t[1 + j] = mu[j];
+  for (int j = 0; j < 6; ++j) t[4 + j] = C[j];
+  t[10] = Nb;
+  q.shift_out[b] = make_float4((float)mu[0], (float)mu[1], (float)mu[2], 0.0f);
+  float *qq = q.cpar_out + (size_t)b * kParStride;
+  if (isfinite(cb)) {
+    store_eblock(qq, mu, P);
+    qq[3] = (float)((cb - a.lnZ) * kLog2e);
+  } else {
+    qq[0] = (float)mu[0]; qq[1] = (float)mu[1]; qq[2] = (float)mu[2];
+    for (int j = 0; j < 6; ++j) qq[4 + j] = 0.0f;
+    qq[10] = 0.0f;
+    qq[3] = -INFINITY;
+  }
+  if (b == 0) {
+    *reinterpret_cast<double *>(q.cpar_out + (size_t)K * kParStride) = a.Chdr;
+    // stopping rule (block 0 holds the log-likelihood column)
+    if (q.conv_next && a.mode == kSoftStats) {
+      const double L = tot[kNStat];
+      unsigned f = *q.conv;
+      if ((f & 2u) && fabs(L - *q.Lprev) <= a.tol_abs) f |= 1u;
+      *q.Lprev = L;
+      *q.conv_next = f | 2u;
     }
   }
 }

@@ -651,6 +651,9 @@ struct Run {
   std::vector<EventPair> *sink = nullptr;  // profiling pairs go here
   bool time_loglik = false;  // also time log-likelihood-only passes
   double tol_abs = 0.0;      // > 0: stopping rule |dL| <= tol_abs
+  int64_t n = 0;             // points
+  bool fused = false;        // lambda > 0: one reduce + update launch per pass
+  int conv_par = 0;          // which flag word holds the current stopping state
 };
 
 // The tile kernel alone (writes the partial rows only).
@@ -714,11 +717,17 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   a.P = r.c.P;
   a.mode = mode;
   a.ncols = L.ncols;
-  // with a tolerance, the soft passes check the converged flag
-  unsigned *conv = (r.tol_abs > 0.0 && mode == kSoftStats) ? at<unsigned>(r.ws, L.counter)
-                                                          : nullptr;
+  // with a tolerance, the soft passes check the converged flag: words 0
+  // and 1 of the counter buffer take turns as the current and the next
+  // state (a full M-step writes the next), the double at word 2 is L_prev
+  unsigned *cbase = at<unsigned>(r.ws, L.counter);
+  unsigned *conv = (r.tol_abs > 0.0 && mode == kSoftStats) ? cbase + r.conv_par : nullptr;
+  unsigned *conv_next = (conv && umode == kUpdFull) ? cbase + (1 - r.conv_par) : nullptr;
+  double *Lprev = conv ? reinterpret_cast<double *>(cbase + 2) : nullptr;
   a.conv = conv;
   const int rows = cull ? r.cc.grid : r.c.grid;  // partial rows written
+  const bool fuse = r.fused && reg > 0.0;
+  a.cmaj = fuse ? 1 : 0;   // the fused reduction reads a component's sums together
   EventPair pp;
   const bool timed = r.sink && (mode == kSoftStats || r.time_loglik);
   if (timed) {
@@ -748,6 +757,40 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   }
   if (timed) HIP_TRY(hipEventRecord(pp.b, r.s));
   const int nxt = 1 - r.cur;
+  if (conv_next) r.conv_par = 1 - r.conv_par;
+  if (fuse) {
+    UpdPtrs q;
+    q.red2 = nullptr;
+    q.cpar_in = at<float>(r.ws, L.cpar[r.cur]);
+    q.shift_in = at<float4>(r.ws, L.shift[r.cur]);
+    q.cpar_out = at<float>(r.ws, L.cpar[nxt]);
+    q.shift_out = at<float4>(r.ws, L.shift[nxt]);
+    q.th64 = at<double>(r.ws, L.th64);
+    q.loglik_slot = loglik_slot;
+    q.out_w = out_w;
+    q.out_mu = out_mu;
+    q.out_cov = out_cov;
+    q.status = at<uint32_t>(r.ws, L.status);
+    q.conv = conv;
+    q.conv_next = conv_next;
+    q.Lprev = Lprev;
+    FuseArgs fa;
+    fa.K = r.K;
+    fa.ncols = L.ncols;
+    fa.nrows = rows;
+    fa.mode = mode;
+    fa.umode = umode;
+    fa.reg = reg;
+    fa.Ntot = (double)r.n + r.K * kEpsN;
+    fa.lnZ = log(fa.Ntot) - 1.5 * log(reg);
+    fa.Chdr = (-1.5 * log(reg) - 1.5 * kLn2Pi) * kLog2e;
+    fa.tol_abs = r.tol_abs;
+    hipLaunchKernelGGL(reduce_update_kernel, dim3(r.K), dim3(kFuseThreads), 0, r.s,
+                       at<double>(r.ws, L.part), q, fa);
+    HIP_TRY(hipGetLastError());
+    if (umode != kUpdNone) r.cur = nxt;
+    return GMM_OK;
+  }
   const int col0 = (mode == kSoftLogLik) ? kNStat * r.K : 0;
   const int ncx = (L.ncols - col0 + 63) / 64;
   hipLaunchKernelGGL(reduce_rows_kernel<1024>, dim3(ncx, kRedChunksFit), dim3(1024), 0,
@@ -767,6 +810,8 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
   q.out_cov = out_cov;
   q.status = at<uint32_t>(r.ws, L.status);
   q.conv = conv;
+  q.conv_next = conv_next;
+  q.Lprev = Lprev;
   UpdArgs ua;
   ua.ncols = L.ncols;
   ua.col0 = col0;
@@ -930,6 +975,12 @@ gmm_status fit_setup(const float *pts, int64_t n, int32_t k, const float *w,
   if (!(opts->tol >= 0.0) || !isfinite(opts->tol))
     return fail(GMM_ERR_INVALID_ARG, "tol must be finite and >= 0");
   r->tol_abs = opts->tol * (double)n;
+  r->n = n;
+  // lambda > 0: the fused reduction + M-step (GMM_FUSED=0 keeps two launches)
+  {
+    const char *e = getenv("GMM_FUSED");
+    r->fused = opts->reg_covar > 0.0 && !(e && e[0] == '0');
+  }
   r->K = k;
   if (!pick_cfg(k, n, &r->c)) return fail(GMM_ERR_UNSUPPORTED, "no launch configuration for k=%d", k);
   r->cull = pick_cull_cfg(k, n, &r->cc);
@@ -951,13 +1002,14 @@ struct FitKey {
   double reg, tol;
   int k, iters, mode, dev;
   const void *dense, *culled;  // the kernels the fit launches
-  bool sorted;
+  bool sorted, fused;
   bool operator==(const FitKey &o) const {
     return pts == o.pts && labels == o.labels && w == o.w && mu == o.mu &&
            cov == o.cov && loglik == o.loglik && ws == o.ws && n == o.n &&
            ws_bytes == o.ws_bytes && reg == o.reg && tol == o.tol && k == o.k &&
            iters == o.iters && mode == o.mode && dev == o.dev &&
-           dense == o.dense && culled == o.culled && sorted == o.sorted;
+           dense == o.dense && culled == o.culled && sorted == o.sorted &&
+           fused == o.fused;
   }
 };
 
@@ -1720,7 +1772,7 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
                opts->reg_covar, opts->tol, k, opts->iters, opts->moment_mode, 0,
                reinterpret_cast<const void *>(r.c.launch),
                r.cull ? reinterpret_cast<const void *>(r.cc.launch) : nullptr,
-               sort_enabled()};
+               sort_enabled(), r.fused};
     (void)hipGetDevice(&key.dev);
     std::lock_guard<std::mutex> lk(g_graph_mu);
     bool found = false;
