@@ -89,6 +89,7 @@ def parse():
     ap.add_argument("--no-kinit", action="store_true")
     ap.add_argument("--no-blobs", action="store_true")
     ap.add_argument("--no-registration", action="store_true")
+    ap.add_argument("--no-meanshift", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device tensor copy "
                          "(a known-size reference for memory counters)")
@@ -342,6 +343,57 @@ def blobs_fit(reps=10):
                              "sample": "the whole 50-iteration fit from the same labels"}}
 
 
+def meanshift_bench(reps=5, cpu=True, cpu_seeds=60):
+    """Component count by mean shift on the 4D depth-intensity frame at the
+    paper's 2x-reduced image size (320 x 240 = 76,800 points, every other
+    pixel of the synthetic 640 x 480 frame), bandwidths 0.015 (the paper's
+    example) and 0.03; median of reps whole calls.  The CPU baseline is the
+    FP64 oracle's per-seed mean shift on a seeded sample of the seeds,
+    scaled to seeds per second (the merge is not timed there)."""
+    import numpy as np
+    import torch
+
+    import paper_2307_00071_amd as gmm
+    from paper_2307_00071_amd import synth
+
+    dev = torch.device("cuda:0")
+    X = np.ascontiguousarray(
+        synth.depth_intensity_frame(0).reshape(480, 640, 4)[::2, ::2].reshape(-1, 4))
+    pts = torch.from_numpy(X).to(dev)
+    ws = torch.empty(gmm.meanshift_workspace_bytes(X.shape[0], 4), dtype=torch.uint8,
+                     device=dev)
+    out = {"workload": "320x240 depth-intensity frame (N=76800, 4D), flat-kernel mean "
+                       "shift over binned seeds, max_iter=300"}
+    for h in (0.015, 0.03):
+        gmm.meanshift(pts, h, workspace=ws)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            _, _, info = gmm.meanshift(pts, h, workspace=ws)
+            times.append(time.perf_counter() - t0)
+        dt = float(np.median(times))
+        r = {"bandwidth": h, "ms": 1e3 * dt, "seeds": info["n_seeds"], "K": info["n_modes"],
+             "merge_rounds": info["rounds"], "max_iters": info["max_iters"],
+             "seeds_per_s": info["n_seeds"] / dt}
+        if cpu:
+            from oracle import gbms as og
+            X64 = X.astype(np.float64)
+            seeds = og.bin_seeds(X64, h)
+            pick = np.random.default_rng(3).choice(seeds.shape[0], cpu_seeds, replace=False)
+            t0 = time.perf_counter()
+            for i in pick:
+                og.shift_seed(X64, seeds[i], h, 300)
+            dto = time.perf_counter() - t0
+            r["cpu_baseline"] = {"seeds_per_s": cpu_seeds / dto,
+                                 "est_ms_all_seeds": 1e3 * dto / cpu_seeds * info["n_seeds"],
+                                 "cores": 1, "kind": "oracle",
+                                 "sample": "%d seeded seeds' mean shift (numpy, "
+                                           "brute-force radius queries)" % cpu_seeds}
+        out["h=%g" % h] = r
+    return out
+
+
 def registration(reps=20, cpu=True):
     """Registration likelihood and gradient: a K = 200 mixture fitted (GPU,
     20 iterations from k-means++ labels) to the depth frame, a source of
@@ -548,6 +600,8 @@ def main():
         out["blobs"] = blobs_fit()
     if not args.no_registration:
         out["registration"] = registration(cpu=not args.no_cpu_baseline)
+    if not args.no_meanshift:
+        out["meanshift"] = meanshift_bench(cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, lab, K, T, args.cpu_seconds)
         out["cpu_baseline_1thread"] = cpu_baseline(X, lab, K, T, 4.0, threads=1)

@@ -348,6 +348,53 @@ gmm_status gmm4_joint_dist_sample(int32_t k, const float *w, const float *mu, co
 gmm_status gmm_set_autotune(int on);
 const char *gmm_tile_config(int64_t n, int32_t k);
 
+/* ---------------------------------------------------- component count
+ * gmm_meanshift: the number of mixture components K for a bandwidth h, by
+ * mean shift with a flat kernel over binned seeds (the paper, Sec. V
+ * "Gaussian Blurring Mean Shift", and its information-flow figure, where the
+ * bandwidth and the point cloud give K before k-means seeding and EM):
+ *   seeds   the centres b h of the occupied bins b = rint(x / h) (FP64
+ *           division, round half to even), in lexicographic order of b;
+ *   shift   a seed moves to the mean of the points within distance h
+ *           (squared distance ((d0^2 + d1^2) + d2^2) (+ d3^2) <= h^2, every
+ *           FP64 operation rounded on its own) until the move is at most
+ *           1e-3 h or its iteration count has reached max_iter; its weight
+ *           is the size of the last neighbourhood (0 when the first one is
+ *           empty: the seed is dropped);
+ *   merge   in the order (weight descending, coordinates descending, seed
+ *           ascending) a mode still kept removes every later mode within
+ *           h; K is the number kept.
+ *  pts          device float32 n x d: d = 3 (x, y, z) or d = 4 (x, y, z,
+ *               intensity).  Every bin index |rint(x / h)| must be at most
+ *               2^20 - 2 (d = 3) or 2^15 - 2 (d = 4), else INVALID_ARG.
+ *  bandwidth    h, finite and > 0.   max_iter >= 0 (a seed takes at most
+ *               max_iter + 1 means).
+ *  modes        device float64 max_modes x d: the kept modes, in seed order;
+ *  weights      device int64 max_modes, or NULL: their weights.  More than
+ *               max_modes kept is INVALID_ARG, with info->n_modes set
+ *               (max_modes = n always suffices).
+ *  seed_modes   device float64 n x d; seed_weights, seed_iters, seed_status:
+ *               device int32 n.  Each NULL, or filled for the
+ *               info->n_seeds seeds: mode, weight, iteration count, and
+ *               1 kept / 2 removed by the merge / 3 dropped.
+ *  info         host: seeds, K, merge rounds, largest iteration count.
+ *  Synchronises: the merge checks its progress on the host every 16 rounds
+ *  and the call returns K.  n = 0 gives K = 0.  FP64 sums in a fixed order:
+ *  bitwise reproducible.  Errors: INVALID_ARG (d, n, h, max_iter, NULL
+ *  pointers, bin range), NONFINITE (a NaN or Inf coordinate), OOM, DEVICE. */
+typedef struct {
+    int64_t n_seeds;    /* occupied bins */
+    int32_t n_modes;    /* K */
+    int32_t rounds;     /* merge rounds until every mode was decided */
+    int32_t max_iters;  /* the largest iteration count of a seed */
+} gmm_meanshift_info;
+size_t gmm_meanshift_workspace_size(int64_t n, int32_t d);
+gmm_status gmm_meanshift(const float *pts, int64_t n, int32_t d, double bandwidth,
+                         int32_t max_iter, double *modes, int64_t *weights, int64_t max_modes,
+                         double *seed_modes, int32_t *seed_weights, int32_t *seed_iters,
+                         int32_t *seed_status, gmm_meanshift_info *info, void *ws,
+                         size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------ profiling
  * Kernel timing for benchmarks.  While enabled (reps >= 1, per calling host
  * thread), every E+M statistics pass of the tile kernel made by gmm_fit, the

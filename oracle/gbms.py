@@ -72,10 +72,34 @@ def shift_seed(X, s, h, max_iter):
     return s, cnt, it
 
 
+def merge(modes, weights, h):
+    """Merge of converged modes given in seed order: the order is weight
+    descending, then coordinates descending (lexicographic), then seed
+    ascending (a stable sort); walking it, a mode still kept removes every
+    later mode within distance h.  Returns (kept mask in seed order, the
+    order as seed indices)."""
+    modes = np.asarray(modes, np.float64)
+    weights = np.asarray(weights)
+    m = len(weights)
+    order = sorted(range(m), key=lambda i: (weights[i], tuple(modes[i])), reverse=True)
+    om = modes[order].reshape(m, -1)
+    keep = np.ones(m, dtype=bool)
+    h2 = float(h) * float(h)
+    for i in range(m):
+        if not keep[i]:
+            continue
+        near = _sqdist(om, om[i]) <= h2
+        near[: i + 1] = False
+        keep[near] = False
+    mask = np.zeros(m, dtype=bool)
+    mask[np.asarray(order, dtype=np.int64)[keep]] = True
+    return mask, np.asarray(order, dtype=np.int64)
+
+
 def gbms(X, bandwidth, max_iter=300):
     """Modes of the point cloud X (N x D, D = 3 or 4) for bandwidth h.
     Returns (modes (K, D) float64 in merge order, weights (K,) int64,
-    all converged (mode, weight) pairs before the merge)."""
+    all converged (mode, weight) pairs before the merge, in merge order)."""
     X = np.asarray(X, np.float64)
     h = float(bandwidth)
     res = []
@@ -83,17 +107,8 @@ def gbms(X, bandwidth, max_iter=300):
         m, c, _ = shift_seed(X, s, h, max_iter)
         if c > 0:
             res.append((m, c))
-    # weight descending, ties by coordinates descending
-    order = sorted(range(len(res)), key=lambda i: (res[i][1], tuple(res[i][0])),
-                   reverse=True)
-    modes = np.array([res[i][0] for i in order]).reshape(-1, X.shape[1])
-    w = np.array([res[i][1] for i in order], dtype=np.int64)
-    keep = np.ones(len(order), dtype=bool)
-    h2 = h * h
-    for i in range(len(order)):
-        if not keep[i]:
-            continue
-        near = _sqdist(modes, modes[i]) <= h2
-        near[: i + 1] = False
-        keep[near] = False
-    return modes[keep], w[keep], (modes, w)
+    modes = np.array([r[0] for r in res]).reshape(-1, X.shape[1])
+    w = np.array([r[1] for r in res], dtype=np.int64)
+    mask, order = merge(modes, w, h)
+    kept = order[mask[order]]
+    return modes[kept], w[kept], (modes[order], w[order])

@@ -14,7 +14,8 @@ import ctypes
 from . import _lib
 
 __all__ = ["fit", "fit_noalloc", "fit_batched", "loglik", "loglik_backward", "GMMLogLik",
-           "FitResult", "kmeanspp", "fit4", "color_conditional", "joint_dist_sample"]
+           "FitResult", "kmeanspp", "fit4", "color_conditional", "joint_dist_sample",
+           "meanshift"]
 
 
 def _torch():
@@ -480,3 +481,49 @@ def joint_dist_sample(w, mu, cov, m, seed=0, u=None, z=None, check=True):
     if check:
         _device_status(ws, dev)
     return out, comp
+
+
+def meanshift_workspace_bytes(n, d):
+    return int(_lib.load().gmm_meanshift_workspace_size(int(n), int(d)))
+
+
+def meanshift(points, bandwidth, max_iter=300, seeds=False, workspace=None):
+    """Number of mixture components for a bandwidth by flat-kernel mean shift
+    over binned seeds (gmm_meanshift).  points: float32 (N, 3) or (N, 4) on
+    the GPU.  Returns (modes float64 (K, d), weights int64 (K,), info dict);
+    the modes are in seed order (lexicographic order of their seeds' bins).
+    seeds=True adds the per-seed results to info: seed_modes (S, d),
+    seed_weights, seed_iters and seed_status (1 kept, 2 removed by the merge,
+    3 dropped), S = info["n_seeds"]."""
+    torch = _torch()
+    lib = _lib.load()
+    if not (hasattr(points, "is_cuda") and points.is_cuda):
+        raise ValueError("points must be a CUDA tensor")
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] not in (3, 4):
+        raise ValueError("points must be float32 (N, 3) or (N, 4)")
+    points = points.contiguous()
+    dev = points.device
+    n, d = points.shape
+    cap = max(n, 1)
+    modes = torch.empty(cap, d, dtype=torch.float64, device=dev)
+    weights = torch.empty(cap, dtype=torch.int64, device=dev)
+    sm = sw = si = ss = None
+    if seeds:
+        sm = torch.empty(cap, d, dtype=torch.float64, device=dev)
+        sw, si, ss = (torch.empty(cap, dtype=torch.int32, device=dev) for _ in range(3))
+    if workspace is None:
+        workspace = _workspace(max(lib.gmm_meanshift_workspace_size(n, d), 256), dev)
+    info = _lib.MeanShiftInfo()
+    _lib.check(lib.gmm_meanshift(
+        _ptr(points) if n else None, n, d, float(bandwidth), int(max_iter), _ptr(modes),
+        _ptr(weights), cap, _ptr(sm) if seeds else None, _ptr(sw) if seeds else None,
+        _ptr(si) if seeds else None, _ptr(ss) if seeds else None, ctypes.byref(info),
+        _ptr(workspace), workspace.numel(), _stream(dev)))
+    K = int(info.n_modes)
+    out = {"n_seeds": int(info.n_seeds), "n_modes": K, "rounds": int(info.rounds),
+           "max_iters": int(info.max_iters)}
+    if seeds:
+        S = out["n_seeds"]
+        out.update(seed_modes=sm[:S], seed_weights=sw[:S], seed_iters=si[:S],
+                   seed_status=ss[:S])
+    return modes[:K], weights[:K], out

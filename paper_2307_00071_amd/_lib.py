@@ -13,6 +13,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgmm.so")
 
 GMM_OK = 0
+GMM_ERR_INVALID_ARG = 1
+GMM_ERR_NOT_SPD = 2
+GMM_ERR_NONFINITE = 3
+GMM_ERR_OOM = 4
+GMM_ERR_DEVICE = 5
+GMM_ERR_UNSUPPORTED = 6
 GMM_MOMENTS_SHIFTED = 0
 GMM_MOMENTS_TWO_PASS = 1
 GMM_FLAG_ASYNC = 1
@@ -32,6 +38,7 @@ EXPORTS = (
     "gmm4_fit_workspace_size", "gmm4_fit",
     "gmm4_color_conditional_workspace_size", "gmm4_color_conditional",
     "gmm4_joint_dist_sample_workspace_size", "gmm4_joint_dist_sample",
+    "gmm_meanshift_workspace_size", "gmm_meanshift",
 )
 
 
@@ -39,6 +46,11 @@ class GmmError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__("gmm status %d: %s" % (status, msg))
         self.status = status
+
+
+class MeanShiftInfo(ctypes.Structure):
+    _fields_ = [("n_seeds", ctypes.c_int64), ("n_modes", ctypes.c_int32),
+                ("rounds", ctypes.c_int32), ("max_iters", ctypes.c_int32)]
 
 
 class FitOpts(ctypes.Structure):
@@ -124,6 +136,11 @@ def load():
     lib.gmm4_joint_dist_sample_workspace_size.restype = sz
     lib.gmm4_joint_dist_sample.argtypes = [i32, vp, vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
     lib.gmm4_joint_dist_sample.restype = ctypes.c_int
+    lib.gmm_meanshift_workspace_size.argtypes = [i64, i32]
+    lib.gmm_meanshift_workspace_size.restype = sz
+    lib.gmm_meanshift.argtypes = [vp, i64, i32, ctypes.c_double, i32, vp, vp, i64,
+                                  vp, vp, vp, vp, ctypes.POINTER(MeanShiftInfo), vp, sz, vp]
+    lib.gmm_meanshift.restype = ctypes.c_int
     _lib = lib
     return lib
 

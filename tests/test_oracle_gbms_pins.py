@@ -100,3 +100,23 @@ def test_merge_rule():
     X2 = np.array([[1.0, 0, 0]] * 3 + [[2.0, 0, 0]] * 3)
     modes2, w2, _ = og.gbms(X2, 0.5)
     np.testing.assert_array_equal(modes2, [[2.0, 0, 0], [1.0, 0, 0]])
+
+
+def test_merge_chain_and_ties():
+    """A removed mode removes nothing: in the chain A (w 5) - B (w 4) - C
+    (w 3), 0.8 apart with h = 1, B goes (A is within h) and C stays (only B
+    is within h of it), which a rule 'drop a mode with any heavier mode
+    within h' would get wrong.  Identical (weight, mode) pairs keep the
+    first seed."""
+    modes = np.array([[1.6, 0, 0], [0.0, 0, 0], [0.8, 0, 0]])
+    w = np.array([3, 5, 4])
+    mask, order = og.merge(modes, w, 1.0)
+    np.testing.assert_array_equal(order, [1, 2, 0])
+    np.testing.assert_array_equal(mask, [True, True, False])
+    dup = np.array([[2.0, 1, 1], [2.0, 1, 1], [2.0, 1, 1]])
+    mask, order = og.merge(dup, np.array([7, 7, 7]), 0.5)
+    np.testing.assert_array_equal(order, [0, 1, 2])
+    np.testing.assert_array_equal(mask, [True, False, False])
+    # exactly h apart: removed (the test is <=)
+    mask, _ = og.merge(np.array([[0.0, 0, 0], [0.5, 0, 0]]), np.array([2, 1]), 0.5)
+    np.testing.assert_array_equal(mask, [True, False])
