@@ -23,11 +23,15 @@ the SE(3) transform; it gives no formulas.  The readings taken here:
               I - (1 - eps) v v^T for v the eigenvector of the smallest
               eigenvalue; hybrid: isoplanar iterations, then anisotropic
               ones from the result;
-  step        one Gauss-Newton step on the EM lower bound of f:
-              gamma_ij = the pair's share of the sum at T, S_ij held at T,
-              residual d_ij = R mu_i + t - nu_j, J_ij = [-[R mu_i]_x, I],
-              H = sum gamma J^T S^-1 J, b = sum gamma J^T S^-1 d,
-              x = -H^-1 b (FP64 Cholesky); trial poses
+  step        a Newton-type ascent step in the left-perturbation
+              coordinates (delta, dt): the curvature is the Gauss-Newton
+              matrix of the EM lower bound of f (gamma_ij = the pair's share
+              of the sum at T, S_ij held at T, residual d_ij = R mu_i + t -
+              nu_j, J_ij = [-[R mu_i]_x, I], H = sum gamma J^T S^-1 J), the
+              right-hand side is the exact gradient (so that the steps stop
+              where f is stationary: with S held fixed the rotation of the
+              covariances would be left out), x = H^-1 grad f (FP64
+              Cholesky); trial poses
               R' = exp([s x_w]_x) R, t' = t + s x_t for s = 1, 1/2, ...,
               2^-7; the first trial with f(T') > f(T) is taken; the stage
               ends when max|x| < 1e-8, when H is not positive definite,
@@ -121,11 +125,10 @@ def objective(pose6, src, tgt):
     return _lse(ell)
 
 
-def objective_grad(pose6, src, tgt):
-    """(f, df/d(omega, t)) at pose6 = (omega, t)."""
-    pose6 = np.asarray(pose6, np.float64)
-    R = expso3(pose6[:3])
-    ell, a, S, d, g, Sp = pair_terms(R, pose6[3:], src, tgt)
+def grad_delta(R, t, src, tgt):
+    """(f, df/d(delta, dt)) for a left perturbation exp([delta]_x) R of R
+    and t + dt."""
+    ell, a, S, d, g, Sp = pair_terms(R, t, src, tgt)
     f = _lse(ell)
     gam = np.exp(ell - f)
     # dl/dt = -g; dl/d delta = g x a + (A_23, A_31, A_12), A = Sigma' M - M Sigma',
@@ -138,26 +141,32 @@ def objective_grad(pose6, src, tgt):
     dl_dd = np.cross(g, ab) + np.stack([A[..., 1, 2], A[..., 2, 0], A[..., 0, 1]], -1)
     gd = np.einsum("ij,ija->a", gam, dl_dd)
     gt = -np.einsum("ij,ija->a", gam, g)
-    gw = left_jacobian(pose6[:3]).T @ gd
-    return f, np.concatenate([gw, gt])
+    return f, np.concatenate([gd, gt])
+
+
+def objective_grad(pose6, src, tgt):
+    """(f, df/d(omega, t)) at pose6 = (omega, t)."""
+    pose6 = np.asarray(pose6, np.float64)
+    f, gdt = grad_delta(expso3(pose6[:3]), pose6[3:], src, tgt)
+    gw = left_jacobian(pose6[:3]).T @ gdt[:3]
+    return f, np.concatenate([gw, gdt[3:]])
 
 
 def gn_system(R, t, src, tgt):
-    """f, H (6 x 6) and b (6) of the Gauss-Newton step at (R, t)."""
+    """f, the Gauss-Newton matrix H (6 x 6) and its right-hand side
+    b = sum gamma J^T S^-1 d at (R, t)."""
     ell, a, S, d, g, _ = pair_terms(R, t, src, tgt)
     f = _lse(ell)
     gam = np.exp(ell - f)
     Sinv = np.linalg.inv(S)
-    H = np.zeros((6, 6))
-    b = np.zeros(6)
-    M, N = ell.shape
+    M = ell.shape[0]
+    J = np.empty((M, 3, 6))                        # d(d_ij)/d(delta, dt), per source i
     for i in range(M):
-        Ax = skew(a[i])
-        J = np.hstack([-Ax, np.eye(3)])            # d(d_ij)/d(delta, dt)
-        for j in range(N):
-            JS = J.T @ Sinv[i, j]
-            H += gam[i, j] * (JS @ J)
-            b += gam[i, j] * (JS @ d[i, j])
+        J[i, :, :3] = -skew(a[i])
+        J[i, :, 3:] = np.eye(3)
+    JS = np.einsum("iak,ijab->ijkb", J, Sinv)      # J^T S^-1
+    H = np.einsum("ij,ijkb,ibl->kl", gam, JS, J)
+    b = np.einsum("ij,ijkb,ijb->k", gam, JS, d)
     return f, H, b
 
 
@@ -182,12 +191,13 @@ def register(T0, src, tgt, iters_iso=30, iters_aniso=30):
         hist.append((name, f))
         done = 0
         for _ in range(n):
-            f0, H, b = gn_system(R, t, s, g)
+            _, H, _ = gn_system(R, t, s, g)
+            _, grad = grad_delta(R, t, s, g)
             try:
                 Lc = np.linalg.cholesky(H)
             except np.linalg.LinAlgError:
                 break
-            x = -np.linalg.solve(Lc.T, np.linalg.solve(Lc, b))
+            x = np.linalg.solve(Lc.T, np.linalg.solve(Lc, grad))
             if np.abs(x).max() < STEP_TOL:
                 break
             took = False
