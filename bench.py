@@ -90,6 +90,7 @@ def parse():
     ap.add_argument("--no-blobs", action="store_true")
     ap.add_argument("--no-registration", action="store_true")
     ap.add_argument("--no-meanshift", action="store_true")
+    ap.add_argument("--no-d2d", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device tensor copy "
                          "(a known-size reference for memory counters)")
@@ -394,6 +395,76 @@ def meanshift_bench(reps=5, cpu=True, cpu_seeds=60):
     return out
 
 
+def d2d_bench(reps=5, cpu=True):
+    """D2D registration of two depth-frame mixtures (K = 100 and K = 1000 on
+    each side; mixtures fitted on the GPU to two renders of the synthetic
+    depth frame, the second moved by a known pose): 10 isoplanar + 30
+    anisotropic iterations, median of reps whole calls; the FP64 oracle's
+    registration timed beside it (K = 100 whole, K = 1000 one objective +
+    gradient evaluation)."""
+    import numpy as np
+    import torch
+
+    import paper_2307_00071_amd as gmm
+    from paper_2307_00071_amd import synth
+
+    dev = torch.device("cuda:0")
+    pose = synth.random_pose(5, max_angle=0.15, max_trans=0.2)
+    out = {"workload": "source/target mixtures of two renders of the depth frame "
+                       "(target moved by |omega| <= 0.15 rad, |t| <= 0.2 m), "
+                       "10 isoplanar + 30 anisotropic Gauss-Newton iterations, FP64"}
+    for K in (100, 1000):
+        mixes = []
+        for noise in (None, 77):
+            X = synth.depth_frame(0, noise_seed=noise) if noise else synth.depth_frame(0)
+            pts = torch.from_numpy(X).to(dev)
+            lab, _ = gmm.kmeanspp(pts, K, seed=1)
+            r = gmm.fit(pts, K, iters=20, labels=lab)
+            mixes.append((r.weights, r.means, r.covariances))
+        w, mu, cov = mixes[1]
+        import math
+        th = float(np.linalg.norm(pose[:3]))
+        k = pose[:3] / th
+        Kx = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+        R = np.eye(3) + math.sin(th) * Kx + (1 - math.cos(th)) * Kx @ Kx
+        Rt = torch.as_tensor(R, dtype=torch.float32, device=dev)
+        tt = torch.as_tensor(pose[3:], dtype=torch.float32, device=dev)
+        tgt = (w, mu @ Rt.T + tt, Rt @ cov @ Rt.T)
+        src = mixes[0]
+        gmm.d2d_register(src, tgt, iters_iso=10, iters_aniso=30)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            T, hist, counts = gmm.d2d_register(src, tgt, iters_iso=10, iters_aniso=30)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        dt = float(np.median(times))
+        Tn = T.cpu().numpy()
+        cn = counts.cpu().numpy()
+        it = int(cn.sum())
+        r = {"K": K, "ms": 1e3 * dt, "iterations": [int(x) for x in cn],
+             "pairs_per_iteration": K * K * 9,
+             "pair_evals_per_s": K * K * (9 * it + 2) / dt,
+             "rot_err_rad": float(np.linalg.norm(Tn[:3, :3] - R)),
+             "trans_err_m": float(np.linalg.norm(Tn[:3, 3] - pose[3:]))}
+        if cpu:
+            from oracle import d2d as od
+            s64 = tuple(a.cpu().numpy().astype(np.float64) for a in src)
+            t64 = tuple(a.cpu().numpy().astype(np.float64) for a in tgt)
+            t0 = time.perf_counter()
+            if K <= 100:
+                od.register(np.eye(4), s64, t64, iters_iso=10, iters_aniso=30)
+                what = "the whole registration"
+            else:
+                od.objective_grad(np.zeros(6), s64, t64)
+                what = "one objective + gradient evaluation (1e6 pairs)"
+            r["cpu_baseline"] = {"ms": 1e3 * (time.perf_counter() - t0), "cores": 1,
+                                 "kind": "oracle", "sample": what}
+        out["K=%d" % K] = r
+    return out
+
+
 def registration(reps=20, cpu=True):
     """Registration likelihood and gradient: a K = 200 mixture fitted (GPU,
     20 iterations from k-means++ labels) to the depth frame, a source of
@@ -590,19 +661,22 @@ def main():
                      "frac_on_evaluated_pairs":
                          achieved * pairs_eval / max(pairs_all, 1) / PEAK_FP32_VECTOR},
     }
-    if not args.no_batched:
-        out["batched"] = batched_vs_plain(args.batched_iters, single_evals_per_s=value)
-    if not args.no_lidar:
-        out["lidar"] = lidar_fit()
-    if not args.no_kinit:
-        out["kinit"] = kinit_bench(cpu=not args.no_cpu_baseline)
-    if not args.no_blobs:
-        out["blobs"] = blobs_fit()
-    if not args.no_registration:
-        out["registration"] = registration(cpu=not args.no_cpu_baseline)
-    if not args.no_meanshift:
-        out["meanshift"] = meanshift_bench(cpu=not args.no_cpu_baseline)
-    if not args.no_cpu_baseline:
+    cpu = not args.no_cpu_baseline
+    sections = [
+        ("batched", not args.no_batched,
+         lambda: batched_vs_plain(args.batched_iters, single_evals_per_s=value)),
+        ("lidar", not args.no_lidar, lidar_fit),
+        ("kinit", not args.no_kinit, lambda: kinit_bench(cpu=cpu)),
+        ("blobs", not args.no_blobs, blobs_fit),
+        ("registration", not args.no_registration, lambda: registration(cpu=cpu)),
+        ("meanshift", not args.no_meanshift, lambda: meanshift_bench(cpu=cpu)),
+        ("d2d", not args.no_d2d, lambda: d2d_bench(cpu=cpu)),
+    ]
+    for name, on, run in sections:
+        if on:
+            out[name] = run()
+            print("bench.py: %s done" % name, file=sys.stderr, flush=True)
+    if cpu:
         out["cpu_baseline"] = cpu_baseline(X, lab, K, T, args.cpu_seconds)
         out["cpu_baseline_1thread"] = cpu_baseline(X, lab, K, T, 4.0, threads=1)
     print(json.dumps(out), flush=True)

@@ -395,6 +395,54 @@ gmm_status gmm_meanshift(const float *pts, int64_t n, int32_t d, double bandwidt
                          int32_t *seed_status, gmm_meanshift_info *info, void *ws,
                          size_t ws_bytes, void *stream);
 
+/* --------------------------------------- registration of two mixtures
+ * Distribution-to-distribution (D2D) registration of a source mixture
+ * (pi_i, mu_i, Sigma_i), i < M, to a target mixture (tau_j, nu_j,
+ * Lambda_j), j < N: the paper's GIRA Registration (Sec. IV) with its
+ * anisotropic, isoplanar and isoplanar-then-anisotropic variants, whose
+ * formulas the paper leaves to its citation.  The objective is
+ *   f(T) = ln sum_ij pi_i tau_j N(R mu_i + t; nu_j, R Sigma_i R^T + Lambda_j),
+ * the log of the integral of the product of the transformed source density
+ * and the target density; isoplanar replaces every covariance by
+ * I - (1 - 1e-3) v v^T, v the eigenvector of its smallest eigenvalue.
+ * All arithmetic is FP64 (inputs are float32 mixtures as the fits return
+ * them); sums are in a fixed order (bitwise reproducible).
+ *  w, mu, cov / tw, tmu, tcov  device float32 M, M x 3, M x 3 x 3 (lower
+ *              triangle read) and N, N x 3, N x 3 x 3; weights > 0.
+ *  1 <= M, N <= 65535.  Neither call synchronises: device-side errors (a
+ *  weight <= 0: INVALID_ARG; S_ij not positive definite: NOT_SPD; a
+ *  non-finite value: NONFINITE) are read with gmm_workspace_status(ws). */
+#define GMM_D2D_ANISOTROPIC 0
+#define GMM_D2D_ISOPLANAR 1
+size_t gmm_d2d_workspace_size(int32_t m, int32_t n);
+/* gmm_d2d_objective: f and its gradient at one pose.
+ *  pose6     device float64 6: (omega, t), R = exp([omega]_x) (Rodrigues).
+ *  variant   GMM_D2D_ANISOTROPIC or GMM_D2D_ISOPLANAR.
+ *  out       device float64 7: f, df/domega (3), df/dt (3); df/domega =
+ *            J_l(omega)^T df/ddelta for a left perturbation exp([delta]_x) R. */
+gmm_status gmm_d2d_objective(const double *pose6, int32_t m, const float *w, const float *mu,
+                             const float *cov, int32_t n, const float *tw, const float *tmu,
+                             const float *tcov, int32_t variant, double *out, void *ws,
+                             size_t ws_bytes, void *stream);
+/* gmm_d2d_register: iters_iso isoplanar iterations, then iters_aniso
+ * anisotropic ones (either may be 0: the pure variants), from T0.  An
+ * iteration: H = sum_ij gamma_ij J^T S_ij^-1 J (gamma_ij the pair's share of
+ * the sum at T, J = [-[R mu_i]_x, I], S_ij at T), x = H^-1 grad f (FP64
+ * Cholesky; grad in (delta, t)), then the first of R' = exp([s x_w]_x) R,
+ * t' = t + s x_t, s = 1, 1/2, ..., 2^-7, with f(T') > f(T).  A stage ends
+ * early when H is not positive definite, max |x| < 1e-8 or no trial
+ * increases f.
+ *  T0, T_out   device float64 4 x 4 row-major transforms (T_out = [R t; 0 1]).
+ *  history     device float64 iters_iso + iters_aniso + 2, or NULL: f at the
+ *              start of each stage and after every accepted iteration, in
+ *              order, NaN after the last.
+ *  counts      device int32 2, or NULL: accepted iterations per stage. */
+gmm_status gmm_d2d_register(const double *T0, int32_t m, const float *w, const float *mu,
+                            const float *cov, int32_t n, const float *tw, const float *tmu,
+                            const float *tcov, int32_t iters_iso, int32_t iters_aniso,
+                            double *T_out, double *history, int32_t *counts, void *ws,
+                            size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------ profiling
  * Kernel timing for benchmarks.  While enabled (reps >= 1, per calling host
  * thread), every E+M statistics pass of the tile kernel made by gmm_fit, the

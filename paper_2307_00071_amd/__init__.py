@@ -15,7 +15,7 @@ from . import _lib
 
 __all__ = ["fit", "fit_noalloc", "fit_batched", "loglik", "loglik_backward", "GMMLogLik",
            "FitResult", "kmeanspp", "fit4", "color_conditional", "joint_dist_sample",
-           "meanshift"]
+           "meanshift", "d2d_objective", "d2d_register"]
 
 
 def _torch():
@@ -527,3 +527,66 @@ def meanshift(points, bandwidth, max_iter=300, seeds=False, workspace=None):
         out.update(seed_modes=sm[:S], seed_weights=sw[:S], seed_iters=si[:S],
                    seed_status=ss[:S])
     return modes[:K], weights[:K], out
+
+
+def _mixture3(mix, dev):
+    torch = _torch()
+    w, mu, cov = (torch.as_tensor(a).to(dev, torch.float32).contiguous() for a in mix)
+    k = w.shape[0]
+    if w.shape != (k,) or mu.shape != (k, 3) or cov.shape != (k, 3, 3):
+        raise ValueError("a mixture is (w (K,), mu (K, 3), cov (K, 3, 3))")
+    return w, mu, cov, k
+
+
+def d2d_objective(pose6, src, tgt, variant="anisotropic", check=True):
+    """f = ln sum_ij pi_i tau_j N(R mu_i + t; nu_j, R Sigma_i R^T + Lambda_j)
+    and df/d(omega, t) at pose6 = (omega, t) (gmm_d2d_objective).  src, tgt:
+    (w, mu, cov) mixtures; variant "anisotropic" or "isoplanar".  Returns
+    (f float, grad float64 numpy (6,))."""
+    torch = _torch()
+    lib = _lib.load()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if hasattr(src[0], "device") and src[0].device.type == "cuda":
+        dev = src[0].device
+    w, mu, cov, m = _mixture3(src, dev)
+    tw, tmu, tcov, n = _mixture3(tgt, dev)
+    var = {"anisotropic": _lib.GMM_D2D_ANISOTROPIC, "isoplanar": _lib.GMM_D2D_ISOPLANAR}[variant]
+    p = torch.as_tensor(pose6, dtype=torch.float64).reshape(6).to(dev)
+    out = torch.empty(7, dtype=torch.float64, device=dev)
+    ws = _workspace(max(lib.gmm_d2d_workspace_size(m, n), 256), dev)
+    _lib.check(lib.gmm_d2d_objective(_ptr(p), m, _ptr(w), _ptr(mu), _ptr(cov), n, _ptr(tw),
+                                     _ptr(tmu), _ptr(tcov), var, _ptr(out), _ptr(ws),
+                                     ws.numel(), _stream(dev)))
+    if check:
+        _device_status(ws, dev)
+    o = out.cpu().numpy()
+    return float(o[0]), o[1:]
+
+
+def d2d_register(src, tgt, T0=None, iters_iso=30, iters_aniso=30, check=True):
+    """Isoplanar then anisotropic D2D registration of the mixture src to tgt
+    from the 4 x 4 transform T0 (identity by default), gmm_d2d_register.
+    Returns (T float64 (4, 4) tensor on the device, history float64 tensor
+    (f per stage start and accepted iteration, NaN after the last), counts
+    int32 tensor (2,))."""
+    import numpy as np
+    torch = _torch()
+    lib = _lib.load()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if hasattr(src[0], "device") and src[0].device.type == "cuda":
+        dev = src[0].device
+    w, mu, cov, m = _mixture3(src, dev)
+    tw, tmu, tcov, n = _mixture3(tgt, dev)
+    T0 = np.eye(4) if T0 is None else T0
+    T0 = torch.as_tensor(T0, dtype=torch.float64).reshape(4, 4).to(dev).contiguous()
+    T = torch.empty(4, 4, dtype=torch.float64, device=dev)
+    hist = torch.empty(iters_iso + iters_aniso + 2, dtype=torch.float64, device=dev)
+    counts = torch.empty(2, dtype=torch.int32, device=dev)
+    ws = _workspace(max(lib.gmm_d2d_workspace_size(m, n), 256), dev)
+    _lib.check(lib.gmm_d2d_register(_ptr(T0), m, _ptr(w), _ptr(mu), _ptr(cov), n, _ptr(tw),
+                                    _ptr(tmu), _ptr(tcov), int(iters_iso), int(iters_aniso),
+                                    _ptr(T), _ptr(hist), _ptr(counts), _ptr(ws), ws.numel(),
+                                    _stream(dev)))
+    if check:
+        _device_status(ws, dev)
+    return T, hist, counts

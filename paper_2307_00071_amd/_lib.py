@@ -25,6 +25,8 @@ GMM_FLAG_ASYNC = 1
 GMM_FLAG_DETERMINISTIC = 2
 GMM_MAX_K = 1024
 GMM_FIT_NOALLOC_MAX_BYTES = 64 << 20
+GMM_D2D_ANISOTROPIC = 0
+GMM_D2D_ISOPLANAR = 1
 
 EXPORTS = (
     "gmm_status_string", "gmm_last_error", "gmm_workspace_status",
@@ -39,6 +41,7 @@ EXPORTS = (
     "gmm4_color_conditional_workspace_size", "gmm4_color_conditional",
     "gmm4_joint_dist_sample_workspace_size", "gmm4_joint_dist_sample",
     "gmm_meanshift_workspace_size", "gmm_meanshift",
+    "gmm_d2d_workspace_size", "gmm_d2d_objective", "gmm_d2d_register",
 )
 
 
@@ -141,6 +144,13 @@ def load():
     lib.gmm_meanshift.argtypes = [vp, i64, i32, ctypes.c_double, i32, vp, vp, i64,
                                   vp, vp, vp, vp, ctypes.POINTER(MeanShiftInfo), vp, sz, vp]
     lib.gmm_meanshift.restype = ctypes.c_int
+    lib.gmm_d2d_workspace_size.argtypes = [i32, i32]
+    lib.gmm_d2d_workspace_size.restype = sz
+    lib.gmm_d2d_objective.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp, i32, vp, vp, sz, vp]
+    lib.gmm_d2d_objective.restype = ctypes.c_int
+    lib.gmm_d2d_register.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp, i32, i32, vp, vp,
+                                     vp, vp, sz, vp]
+    lib.gmm_d2d_register.restype = ctypes.c_int
     _lib = lib
     return lib
 

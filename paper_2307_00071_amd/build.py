@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("gmm.hip", "gmm4.hip", "gbms.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("gmm.hip", "gmm4.hip", "gbms.hip", "d2d.hip")]
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmm.so")
 ARCH = "gfx950"

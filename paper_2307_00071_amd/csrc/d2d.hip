@@ -1,0 +1,227 @@
+// MI355X (gfx950) distribution-to-distribution registration of two Gaussian
+// mixtures: host side of the C ABI calls gmm_d2d_objective and
+// gmm_d2d_register (include/gmm.h).  Kernels in d2d_device.hpp.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "d2d_device.hpp"
+#include "gmm.h"
+
+namespace gmm_host {
+extern thread_local char g_err[512];
+}
+
+namespace {
+
+using namespace d2d_dev;
+using gmm_host::g_err;
+
+gmm_status fail(gmm_status s, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+#define HIP_TRY(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail(GMM_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_));   \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <typename T>
+T *at(void *ws, size_t off) {
+  return reinterpret_cast<T *>(static_cast<unsigned char *>(ws) + off);
+}
+
+constexpr int kMaxComp = 65535;   // grid.x = source components
+
+// Workspace: the state first (its status word at offset 0), then the two
+// mixtures in FP64 and the per-block rows.
+struct D2DLayout {
+  size_t state, src, tgt, rows, total;
+};
+
+D2DLayout d2d_layout(int m, int n) {
+  D2DLayout L;
+  size_t o = 0;
+  L.state = o; o = align256(o + sizeof(State));
+  L.src = o;   o = align256(o + (size_t)m * 10 * sizeof(double));
+  L.tgt = o;   o = align256(o + (size_t)n * 10 * sizeof(double));
+  L.rows = o;  o = align256(o + (size_t)m * std::max(2 * kTrials, kNStat) * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+gmm_status check_mix(int m, const float *w, const float *mu, const float *cov, const char *who) {
+  if (m < 1 || m > kMaxComp)
+    return fail(GMM_ERR_INVALID_ARG, "%s: component count %d outside [1, %d]", who, m, kMaxComp);
+  if (!w || !mu || !cov) return fail(GMM_ERR_INVALID_ARG, "%s: NULL mixture pointer", who);
+  return GMM_OK;
+}
+
+Mix mix_of(void *ws, size_t off, int n) {
+  double *b = at<double>(ws, off);
+  return Mix{b, b + n, b + 4 * (size_t)n, n};
+}
+
+gmm_status prep(void *ws, const D2DLayout &L, int m, const float *w, const float *mu,
+                const float *cov, int n, const float *tw, const float *tmu,
+                const float *tcov, int iso, hipStream_t s) {
+  State *st = at<State>(ws, L.state);
+  const Mix a = mix_of(ws, L.src, m), b = mix_of(ws, L.tgt, n);
+  hipLaunchKernelGGL(d2d_prep_kernel, dim3((m + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                     w, mu, cov, m, iso, const_cast<double *>(a.lw),
+                     const_cast<double *>(a.mu), const_cast<double *>(a.cov), &st->status);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(d2d_prep_kernel, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                     tw, tmu, tcov, n, iso, const_cast<double *>(b.lw),
+                     const_cast<double *>(b.mu), const_cast<double *>(b.cov), &st->status);
+  HIP_TRY(hipGetLastError());
+  return GMM_OK;
+}
+
+// f at poses p0 .. p0 + np - 1 into fval.
+gmm_status value(void *ws, const D2DLayout &L, int m, int n, int p0, int np, hipStream_t s) {
+  State *st = at<State>(ws, L.state);
+  const Mix a = mix_of(ws, L.src, m), b = mix_of(ws, L.tgt, n);
+  double *rows = at<double>(ws, L.rows);
+  hipLaunchKernelGGL(d2d_value_kernel, dim3(m, np), dim3(kThreads), 0, s, a, b, st, p0, rows);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(d2d_value_reduce_kernel, dim3(np), dim3(kThreads), 0, s, st, p0, rows, m);
+  HIP_TRY(hipGetLastError());
+  return GMM_OK;
+}
+
+gmm_status stats_step(void *ws, const D2DLayout &L, int m, int n, const double *pose6,
+                      double *out7, hipStream_t s) {
+  State *st = at<State>(ws, L.state);
+  const Mix a = mix_of(ws, L.src, m), b = mix_of(ws, L.tgt, n);
+  double *rows = at<double>(ws, L.rows);
+  hipLaunchKernelGGL(d2d_stats_kernel, dim3(m), dim3(kThreads), 0, s, a, b, st, rows);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(d2d_step_kernel, dim3(1), dim3(kStepThreads), 0, s, st, rows, m, pose6,
+                     out7);
+  HIP_TRY(hipGetLastError());
+  return GMM_OK;
+}
+
+struct WsGuard {
+  void *ptr = nullptr;
+  hipStream_t s = nullptr;
+  ~WsGuard() {
+    if (ptr) (void)hipFreeAsync(ptr, s);
+  }
+};
+
+gmm_status get_ws(void **ws, size_t *ws_bytes, size_t need, hipStream_t s, WsGuard *g) {
+  if (*ws == nullptr) {
+    const char *fi = getenv("GMM_FAULT_INJECT");
+    if (fi && strcmp(fi, "oom") == 0)
+      return fail(GMM_ERR_OOM, "hipMallocAsync(%zu) failed (GMM_FAULT_INJECT=oom)", need);
+    void *p = nullptr;
+    if (hipMallocAsync(&p, need, s) != hipSuccess)
+      return fail(GMM_ERR_OOM, "hipMallocAsync(%zu) failed", need);
+    g->ptr = p;
+    g->s = s;
+    *ws = p;
+    *ws_bytes = need;
+  }
+  if (*ws_bytes < need)
+    return fail(GMM_ERR_OOM, "workspace %zu bytes < %zu needed", *ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(*ws) & 255)
+    return fail(GMM_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  return GMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gmm_d2d_workspace_size(int32_t m, int32_t n) {
+  if (m < 1 || n < 1 || m > kMaxComp || n > kMaxComp) return 0;
+  return d2d_layout(m, n).total;
+}
+
+gmm_status gmm_d2d_objective(const double *pose6, int32_t m, const float *w, const float *mu,
+                             const float *cov, int32_t n, const float *tw, const float *tmu,
+                             const float *tcov, int32_t variant, double *out, void *ws,
+                             size_t ws_bytes, void *stream) {
+  g_err[0] = 0;
+  gmm_status e;
+  if ((e = check_mix(m, w, mu, cov, "source")) != GMM_OK) return e;
+  if ((e = check_mix(n, tw, tmu, tcov, "target")) != GMM_OK) return e;
+  if (!pose6 || !out) return fail(GMM_ERR_INVALID_ARG, "pose6 and out must not be NULL");
+  if (variant != GMM_D2D_ANISOTROPIC && variant != GMM_D2D_ISOPLANAR)
+    return fail(GMM_ERR_INVALID_ARG, "variant must be GMM_D2D_ANISOTROPIC or GMM_D2D_ISOPLANAR");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const D2DLayout L = d2d_layout(m, n);
+  WsGuard guard;
+  if ((e = get_ws(&ws, &ws_bytes, L.total, s, &guard)) != GMM_OK) return e;
+  State *st = at<State>(ws, L.state);
+  hipLaunchKernelGGL(d2d_init_kernel, dim3(1), dim3(64), 0, s, st, (const double *)nullptr,
+                     pose6, (double *)nullptr, 0, (int *)nullptr);
+  HIP_TRY(hipGetLastError());
+  if ((e = prep(ws, L, m, w, mu, cov, n, tw, tmu, tcov, variant == GMM_D2D_ISOPLANAR, s)) != GMM_OK)
+    return e;
+  if ((e = value(ws, L, m, n, 0, 1, s)) != GMM_OK) return e;
+  hipLaunchKernelGGL(d2d_take_f_kernel, dim3(1), dim3(64), 0, s, st, (double *)nullptr, 0);
+  HIP_TRY(hipGetLastError());
+  return stats_step(ws, L, m, n, pose6, out, s);
+}
+
+gmm_status gmm_d2d_register(const double *T0, int32_t m, const float *w, const float *mu,
+                            const float *cov, int32_t n, const float *tw, const float *tmu,
+                            const float *tcov, int32_t iters_iso, int32_t iters_aniso,
+                            double *T_out, double *history, int32_t *counts, void *ws,
+                            size_t ws_bytes, void *stream) {
+  g_err[0] = 0;
+  gmm_status e;
+  if ((e = check_mix(m, w, mu, cov, "source")) != GMM_OK) return e;
+  if ((e = check_mix(n, tw, tmu, tcov, "target")) != GMM_OK) return e;
+  if (!T0 || !T_out) return fail(GMM_ERR_INVALID_ARG, "T0 and T_out must not be NULL");
+  if (iters_iso < 0 || iters_aniso < 0 || iters_iso > 100000 || iters_aniso > 100000)
+    return fail(GMM_ERR_INVALID_ARG, "iteration counts must be in [0, 100000]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const D2DLayout L = d2d_layout(m, n);
+  WsGuard guard;
+  if ((e = get_ws(&ws, &ws_bytes, L.total, s, &guard)) != GMM_OK) return e;
+  State *st = at<State>(ws, L.state);
+  const int hist_len = iters_iso + iters_aniso + 2;
+  hipLaunchKernelGGL(d2d_init_kernel, dim3(1), dim3(256), 0, s, st, T0, (const double *)nullptr,
+                     history, history ? hist_len : 0, counts);
+  HIP_TRY(hipGetLastError());
+  const int iters[2] = {iters_iso, iters_aniso};
+  for (int stage = 0; stage < 2; ++stage) {
+    if (iters[stage] == 0) continue;
+    if ((e = prep(ws, L, m, w, mu, cov, n, tw, tmu, tcov, stage == 0, s)) != GMM_OK) return e;
+    hipLaunchKernelGGL(d2d_stage_kernel, dim3(1), dim3(64), 0, s, st, stage);
+    HIP_TRY(hipGetLastError());
+    if ((e = value(ws, L, m, n, 0, 1, s)) != GMM_OK) return e;
+    hipLaunchKernelGGL(d2d_take_f_kernel, dim3(1), dim3(64), 0, s, st, history, hist_len);
+    HIP_TRY(hipGetLastError());
+    for (int it = 0; it < iters[stage]; ++it) {
+      if ((e = stats_step(ws, L, m, n, nullptr, nullptr, s)) != GMM_OK) return e;
+      if ((e = value(ws, L, m, n, 1, kTrials, s)) != GMM_OK) return e;
+      hipLaunchKernelGGL(d2d_accept_kernel, dim3(1), dim3(64), 0, s, st, history, hist_len);
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  hipLaunchKernelGGL(d2d_out_kernel, dim3(1), dim3(64), 0, s, st, T_out, counts);
+  HIP_TRY(hipGetLastError());
+  return GMM_OK;
+}
+
+}  // extern "C"
