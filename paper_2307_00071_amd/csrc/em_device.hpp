@@ -52,12 +52,14 @@ enum UpdMode { kUpdFull = 0, kUpdMeanOnly = 1, kUpdNone = 2 };
 //   [0..2] mu  [3] (c_b - C) * log2(e)  [4..9] s * P (P00 P10 P11 P20 P21 P22)
 //   [10] an upper bound of the Frobenius norm of s * P (tile culling)
 // with s = sqrt(log2(e) / 2), c_b = ln pi_b - 3/2 ln 2pi + sum_j ln P_jj
-// (eq. 3) and a bound C >= max_b c_b, so [3] - |P' (x - mu)|^2 =
-// log2(e)(l_nb - C) <= 0.  After the K blocks: C * log2(e) as a double.
-// C is max_b c_b for caller parameters and lambda = 0, and the static bound
-// 3/2 ln(1 / lambda) - 3/2 ln 2pi for parameters from an M-step with
-// lambda > 0 (every eigenvalue of such a Sigma_b is at least lambda, so
-// prod_j P_jj <= lambda^-3/2, and pi_b <= 1).
+// (eq. 3) and a reference C, so [3] - |P' (x - mu)|^2 = log2(e)(l_nb - C).
+// After the K blocks: C * log2(e) as a double.  C is max_b c_b for caller
+// parameters and for lambda = 0 (then [3] <= 0), and the static
+// 3/2 ln(1 / lambda) - 3/2 ln 2pi - ln K for parameters from an M-step with
+// lambda > 0: every eigenvalue of such a Sigma_b is at least lambda, so
+// prod_j P_jj <= lambda^-3/2, and pi_b <= 1, hence [3] <= log2 K (a point's
+// sum of 2^[3] terms stays below K^2, far from FP32 overflow) while a
+// typical weight 1/K keeps [3] near 0, where its float32 rounding is small.
 // Shift array: the FP32 point the M-phase subtracts, per component.
 // FP64 state ("th64"), per component (16 doubles):
 //   [0] pi  [1..3] mu  [4..9] Sigma lower (00 10 11 20 21 22)  [10] N_b
@@ -1510,11 +1512,12 @@ __device__ __forceinline__ void update_body(const UpdPtrs &q, const UpdArgs &a,
 
 // ------------------------------------------- fused reduction and M-step
 // For lambda > 0 the M-step of a component needs no other component: the
-// bound C is the static one above, and sum_a N_a is n + K eps_N (each
-// point's responsibilities sum to one).  The tile pass then writes its
-// partial rows component-major (a component's ten sums adjacent), and one
-// block per component sums its ten columns over the rows and updates it in
-// FP64: thread (g, s) takes statistic s of the rows g, g + G, g + 2G, ...
+// bound C is static (from lambda and K: c_b <= C + ln K), and sum_a N_a is
+// n + K eps_N (each point's responsibilities sum to one).  The tile pass
+// then writes its partial rows component-major (a component's ten sums
+// adjacent), and one block per component sums its ten columns over the
+// rows and updates it in FP64: thread (g, s) takes statistic s of the rows
+// g, g + G, g + 2G, ...
 // (G = kFuseGroups, added in row order), the G group sums are added by a
 // fixed pairwise tree; block 0's last wave also sums the log-likelihood
 // column (lane l the rows l, l + 64, ..., then a fixed butterfly).  One
@@ -1526,7 +1529,7 @@ constexpr int kFuseThreads = kNStat * kFuseGroups + 64;   // then one wave for L
 struct FuseArgs {
   int K, ncols, nrows, mode, umode;
   double reg;
-  double lnZ;      // ln(n + K eps_N) - 3/2 ln(lambda): c_b - C = ln(N_b P00 P11 P22) - lnZ
+  double lnZ;      // ln(n + K eps_N) - 3/2 ln(lambda) - ln K: c_b - C = ln(N_b P00 P11 P22) - lnZ
   double Ntot;     // n + K eps_N
   double Chdr;     // C log2(e)
   double tol_abs;  // as UpdArgs

@@ -781,9 +781,13 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
     fa.mode = mode;
     fa.umode = umode;
     fa.reg = reg;
+    // the bound C = -3/2 ln(lambda) - 3/2 ln(2 pi) - ln K: every c_b is at
+    // most C + ln K (the largest term of a point's sum at most K in value,
+    // the sum at most K^2: no FP32 overflow), and a typical weight 1/K puts
+    // c_b - C near 0, where its float32 rounding is smallest
     fa.Ntot = (double)r.n + r.K * kEpsN;
-    fa.lnZ = log(fa.Ntot) - 1.5 * log(reg);
-    fa.Chdr = (-1.5 * log(reg) - 1.5 * kLn2Pi) * kLog2e;
+    fa.lnZ = log(fa.Ntot) - 1.5 * log(reg) - log((double)r.K);
+    fa.Chdr = (-1.5 * log(reg) - 1.5 * kLn2Pi - log((double)r.K)) * kLog2e;
     fa.tol_abs = r.tol_abs;
     hipLaunchKernelGGL(reduce_update_kernel, dim3(r.K), dim3(kFuseThreads), 0, r.s,
                        at<double>(r.ws, L.part), q, fa);
