@@ -58,6 +58,10 @@ FLOP_PER_EVAL = 42          # distance 19 + log-sum-exp 3 + statistics 20
 FLOP_PER_EVAL_FWD = 22      # registration forward: distance 19 + log-sum-exp 3
 FLOP_PER_EVAL_BWD = 57      # backward: forward 22 + gradient terms 15 + statistics 20
 PEAK_FP32_VECTOR = 157.3    # TFLOP/s, MI355X FP32 vector (packed FMA rate)
+PEAK_FP64_VECTOR = 78.6     # TFLOP/s, MI355X FP64 vector
+FLOP_PER_EVAL_4D = 76       # 4D: E-step 34, log-sum-exp 3, statistics 39
+D2D_FLOP_VALUE = 45         # FP64 per pair term of a D2D value pass
+D2D_FLOP_STATS = 290        # FP64 per pair term of the D2D statistics pass
 PEAK_FP32_NONPACKED = 78.6  # TFLOP/s, one FP32 FMA per lane per cycle
 PROFILE_REPS = 16           # tile launches per timed event pair
 
@@ -89,6 +93,7 @@ def parse():
     ap.add_argument("--no-kinit", action="store_true")
     ap.add_argument("--no-blobs", action="store_true")
     ap.add_argument("--no-registration", action="store_true")
+    ap.add_argument("--no-model4d", action="store_true")
     ap.add_argument("--no-meanshift", action="store_true")
     ap.add_argument("--no-d2d", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -344,6 +349,85 @@ def blobs_fit(reps=10):
                              "sample": "the whole 50-iteration fit from the same labels"}}
 
 
+def model4d_bench(reps=5, cpu=True):
+    """The paper's 4D (x, y, z, intensity) model on the synthetic
+    depth-intensity frame: EM fits at the full 640 x 480 frame and at the
+    2x-reduced 320 x 240 image (every other pixel), K = 100, T = 100, from
+    k-means++ labels of the xyz part; then the conditional intensity at every
+    pixel's location and 640 x 480 joint samples (the paper's examples).
+    Fits replayed as captured graphs, median of reps; the whole-iteration
+    time stands in for the tile kernel in the roofline figure (a lower bound
+    of the kernel's rate).  The FP64 4D
+    oracle (numpy) is timed on 2 iterations of the 320 x 240 fit."""
+    import numpy as np
+    import torch
+
+    import paper_2307_00071_amd as gmm
+    from paper_2307_00071_amd import synth
+
+    dev = torch.device("cuda:0")
+    X = synth.depth_intensity_frame(0)
+    out = {"workload": "synthetic depth-intensity frame, 4D EM K=100 T=100 lambda=1e-3 "
+                       "from k-means++ labels of xyz; conditional intensity; joint sampling"}
+    K, T = 100, 100
+    for name, Xs in (("640x480", X), ("320x240", X.reshape(480, 640, 4)[::2, ::2].reshape(-1, 4))):
+        Xs = np.ascontiguousarray(Xs)
+        N = Xs.shape[0]
+        pts = torch.from_numpy(Xs).to(dev)
+        lab, _ = gmm.kmeanspp(torch.from_numpy(np.ascontiguousarray(Xs[:, :3])).to(dev), K, seed=1)
+        ws = torch.empty(gmm.fit4_workspace_bytes(N, K, T), dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            r = gmm.fit4(pts, K, iters=T, labels=lab, workspace=ws)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = gmm.fit4(pts, K, iters=T, labels=lab, workspace=ws)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        dt = float(np.median(times))
+        evals = N * K * T
+        ach = FLOP_PER_EVAL_4D * N * K / (dt / T) / 1e12
+        sec = {"N": N, "K": K, "iters": T, "ms_per_fit": 1e3 * dt, "evals_per_s": evals / dt,
+               "final_loglik": float(r.loglik[-1].item()),
+               "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VECTOR,
+                            "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VECTOR,
+                            "kernel": "whole EM iteration (4D tile kernel + reduction + update)",
+                            "flop_per_eval": FLOP_PER_EVAL_4D}}
+        if name == "320x240":
+            locs = pts[:, :3].contiguous()
+            gmm.color_conditional(locs, r.weights, r.means, r.covariances)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                gmm.color_conditional(locs, r.weights, r.means, r.covariances)
+            torch.cuda.synchronize()
+            sec["color_conditional_ms"] = 1e3 * (time.perf_counter() - t0) / reps
+            rng = np.random.default_rng(2)
+            m = 640 * 480
+            u = torch.from_numpy(rng.random(m)).to(dev)
+            z = torch.from_numpy(rng.standard_normal((m, 4)).astype(np.float32)).to(dev)
+            gmm.joint_dist_sample(r.weights, r.means, r.covariances, m, u=u, z=z)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                gmm.joint_dist_sample(r.weights, r.means, r.covariances, m, u=u, z=z)
+            torch.cuda.synchronize()
+            sec["joint_dist_sample_640x480_ms"] = 1e3 * (time.perf_counter() - t0) / reps
+            if cpu:
+                from oracle import gmm4 as o4
+                labn = lab.cpu().numpy()
+                t0 = time.perf_counter()
+                o4.fit(Xs.astype(np.float64), K, 1e-3, 2, labels=labn)
+                dto = time.perf_counter() - t0
+                sec["cpu_baseline"] = {"ms_per_iteration": 1e3 * dto / 3, "cores": 1,
+                                       "kind": "oracle",
+                                       "sample": "label M-step + 2 EM iterations of the same fit "
+                                                 "(numpy FP64), per pass"}
+        out[name] = sec
+    return out
+
+
 def meanshift_bench(reps=5, cpu=True, cpu_seeds=60):
     """Component count by mean shift on the 4D depth-intensity frame at the
     paper's 2x-reduced image size (320 x 240 = 76,800 points, every other
@@ -443,9 +527,17 @@ def d2d_bench(reps=5, cpu=True):
         Tn = T.cpu().numpy()
         cn = counts.cpu().numpy()
         it = int(cn.sum())
+        # FP64 work: a value-pass pair term ~45 FLOP (+ log, exp), a
+        # statistics-pass pair term ~290 FLOP (+ log, exp); per iteration one
+        # statistics pass and eight value passes, per stage one value pass
+        flop = K * K * (it * (D2D_FLOP_STATS + 8 * D2D_FLOP_VALUE) + 2 * D2D_FLOP_VALUE)
         r = {"K": K, "ms": 1e3 * dt, "iterations": [int(x) for x in cn],
              "pairs_per_iteration": K * K * 9,
              "pair_evals_per_s": K * K * (9 * it + 2) / dt,
+             "roofline": {"bound": "fp64 alu", "achieved": flop / dt / 1e12,
+                          "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
+                          "frac": flop / dt / 1e12 / PEAK_FP64_VECTOR,
+                          "kernel": "whole registration (all its launches)"},
              "rot_err_rad": float(np.linalg.norm(Tn[:3, :3] - R)),
              "trans_err_m": float(np.linalg.norm(Tn[:3, 3] - pose[3:]))}
         if cpu:
@@ -669,6 +761,7 @@ def main():
         ("kinit", not args.no_kinit, lambda: kinit_bench(cpu=cpu)),
         ("blobs", not args.no_blobs, blobs_fit),
         ("registration", not args.no_registration, lambda: registration(cpu=cpu)),
+        ("model4d", not args.no_model4d, lambda: model4d_bench(cpu=cpu)),
         ("meanshift", not args.no_meanshift, lambda: meanshift_bench(cpu=cpu)),
         ("d2d", not args.no_d2d, lambda: d2d_bench(cpu=cpu)),
     ]

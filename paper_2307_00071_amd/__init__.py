@@ -376,12 +376,19 @@ def kmeanspp(points, k, seed=0, u=None, workspace=None):
 
 # ------------------------------------------------------------- 4D model
 
+def fit4_workspace_bytes(n, k, iters=100, reg_covar=1e-3):
+    opts = _lib.FitOpts(int(iters), float(reg_covar), 0, 0)
+    return int(_lib.load().gmm4_fit_workspace_size(int(n), int(k), ctypes.byref(opts)))
+
+
 def fit4(points, k, iters=100, reg_covar=1e-3, labels=None, theta0=None,
-         moment_mode="shifted", sync=True):
+         moment_mode="shifted", sync=True, workspace=None):
     """EM fit of a K-component 4D mixture to ``points`` (float32 (N, 4) =
     (x, y, z, intensity) on the GPU); start from hard ``labels`` or from
     ``theta0 = (w (K,), mu (K, 4), cov (K, 4, 4))``.  Returns a FitResult
-    with means (K, 4) and covariances (K, 4, 4)."""
+    with means (K, 4) and covariances (K, 4, 4).  With a caller-held
+    ``workspace`` (uint8 tensor of at least fit4_workspace_bytes), repeated
+    calls replay a captured graph."""
     torch = _torch()
     lib = _lib.load()
     if not isinstance(points, torch.Tensor) or not points.is_cuda:
@@ -415,7 +422,8 @@ def fit4(points, k, iters=100, reg_covar=1e-3, labels=None, theta0=None,
     if need == 0:
         _lib.check(lib.gmm4_fit(None, n, k, None, None, None, None, None,
                                 ctypes.byref(opts), None, 0, None))
-    ws = _workspace(need, dev)
+    ws = workspace if workspace is not None and workspace.numel() >= need \
+        else _workspace(need, dev)
     _lib.check(lib.gmm4_fit(_ptr(pts), n, k, _ptr(lab), _ptr(w), _ptr(mu), _ptr(cov),
                             _ptr(L), ctypes.byref(opts), _ptr(ws), ws.numel(),
                             _stream(dev)))
@@ -456,8 +464,8 @@ def color_conditional(locs, w, mu, cov, check=True):
 def joint_dist_sample(w, mu, cov, m, seed=0, u=None, z=None, check=True):
     """m samples (float32 (m, 4)) of a 4D mixture and their components
     (int32 (m,)).  The draws: u (m,) uniforms in [0, 1) choose the component,
-    z (m, 4) standard normals the offset; by default both come from
-    numpy's default_rng(seed) (u first, then z)."""
+    z (m, 4) standard normals the offset (numpy arrays or device tensors); by
+    default both come from numpy's default_rng(seed) (u first, then z)."""
     import numpy as np
     torch = _torch()
     lib = _lib.load()
@@ -468,8 +476,10 @@ def joint_dist_sample(w, mu, cov, m, seed=0, u=None, z=None, check=True):
         rng = np.random.default_rng(seed)
         u = rng.random(m) if u is None else u
         z = rng.standard_normal((m, 4)) if z is None else z
-    u = torch.as_tensor(np.asarray(u, np.float64)).to(dev)
-    z = torch.as_tensor(np.asarray(z, np.float32)).to(dev).contiguous()
+    u = (u.to(dev, torch.float64) if torch.is_tensor(u)
+         else torch.as_tensor(np.asarray(u, np.float64)).to(dev)).contiguous()
+    z = (z.to(dev, torch.float32) if torch.is_tensor(z)
+         else torch.as_tensor(np.asarray(z, np.float32)).to(dev)).contiguous()
     if u.shape != (m,) or z.shape != (m, 4):
         raise ValueError("u must be (m,) and z (m, 4)")
     out = torch.empty(m, 4, dtype=torch.float32, device=dev)

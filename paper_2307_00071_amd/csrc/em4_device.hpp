@@ -90,6 +90,7 @@ __device__ __forceinline__ float logterm4(const float *__restrict__ q, float4 x)
 struct Tile4Args {
   int64_t n;      // points
   int ntiles, K, P, mode, ncols;
+  int cmaj = 0;   // partial row component-major (b kNStat + j), for the fused update
 };
 
 // LDS: E rows (K x kTS floats), Xs (kTS float4), Rs (kTS floats),
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void em4_tile_kernel(
       for (int i = tid; i < K; i += kBlock) {
         double sum = 0.0;
         for (int qq = 0; qq < P; ++qq) sum += Dd[qq * K + i];
-        row[j * K + i] = sum;
+        row[a.cmaj ? i * kNStat + j : j * K + i] = sum;
       }
     }
   }
@@ -427,6 +428,141 @@ __global__ __launch_bounds__(kUpdThreads) void update4_kernel(
     const double Cmax = isfinite(mx) ? (mx - log(sN) - 2.0 * kLn2Pi) * kLog2e : 0.0;
     *reinterpret_cast<double *>(cpar_out + (size_t)K * kPar) = Cmax;
   }
+}
+
+// Fused reduction and M-step for lambda > 0 (one launch per pass instead of
+// reduce4_kernel + update4_kernel).  Every eigenvalue of an updated Sigma_b
+// is at least lambda, so prod_j P_jj <= lambda^-2 and, with pi_b <= 1,
+// c_b <= C + ln K for the static C = -2 ln(lambda) - 2 ln(2 pi) - ln K: the
+// stored c_b - C is at most log2 K (no FP32 overflow of a point's sum) and
+// near 0 for a typical weight 1/K; sum_a N_a = n + K eps (each point's
+// responsibilities sum to one).  So each component is updated on its own:
+// block b sums its 15 columns of the component-major partial rows (thread
+// (g, s) statistic s of rows g, g + G, ..., 16 loads in flight, then a
+// fixed pairwise tree over the G groups), thread 0 updates it in FP64; the
+// last wave of block 0 sums the log-likelihood column.  Bitwise
+// reproducible.
+constexpr int kFuse4Groups = 32;
+constexpr int kFuse4Lwave = (kNStat * kFuse4Groups + 63) / 64 * 64;   // first thread of the L wave
+constexpr int kFuse4Threads = kFuse4Lwave + 64;
+
+struct Fuse4Args {
+  int K, ncols, nrows, mode, umode;
+  double reg;
+  double lnZ;    // ln(n + K eps) - 2 ln(lambda) - ln K: c_b - C = ln(N_b prod P_jj) - lnZ
+  double Ntot;   // n + K eps
+  double Chdr;   // C log2(e)
+};
+
+__global__ __launch_bounds__(kFuse4Threads) void reduce_update4_kernel(
+    const double *__restrict__ part, const float *__restrict__ cpar_in,
+    const float4 *__restrict__ shift_in, float *__restrict__ cpar_out,
+    float4 *__restrict__ shift_out, double *__restrict__ th64, double *loglik_slot,
+    float *out_w, float *out_mu, float *out_cov, uint32_t *status, Fuse4Args a) {
+  __shared__ double sums[kFuse4Groups * kNStat];
+  __shared__ double tot[kNStat + 1];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int K = a.K, b = blockIdx.x;
+  const bool lcol = b == 0 && a.mode != kLabels;
+  const bool stats = a.mode != kSoftLogLik;
+  constexpr int NS = kNStat * kFuse4Groups;
+  if (tid < NS) {
+    if (stats) {
+      const int g = tid / kNStat, st = tid - g * kNStat;
+      const double *src = part + (size_t)b * kNStat + st;
+      constexpr int G = kFuse4Groups;
+      double acc = 0.0;
+      for (int r = g; r < a.nrows; r += 16 * G) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          v[u] = (r + u * G < a.nrows) ? src[(size_t)(r + u * G) * a.ncols] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += v[u];
+      }
+      sums[tid] = acc;
+    }
+  } else if (tid >= kFuse4Lwave && lcol) {   // one whole wave
+    const double *src = part + (size_t)kNStat * K;
+    double acc = 0.0;
+    for (int r = lane; r < a.nrows; r += 16 * 64) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        v[u] = (r + u * 64 < a.nrows) ? src[(size_t)(r + u * 64) * a.ncols] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += v[u];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) tot[kNStat] = acc;
+  }
+#pragma unroll
+  for (int half = kFuse4Groups / 2; half > 0; half >>= 1) {
+    __syncthreads();
+    if (stats && tid < half * kNStat) sums[tid] += sums[tid + half * kNStat];
+  }
+  if (stats && tid < kNStat) tot[tid] = sums[tid];
+  __syncthreads();
+  if (tid != 0) return;
+  if (lcol && loglik_slot) {
+    const double L = tot[kNStat];
+    *loglik_slot = L;
+    if (!isfinite(L)) set_status(status, kStNonFinite);
+  }
+  if (a.umode == kUpdNone) {
+    if (out_w) {
+      const double *t = th64 + (size_t)b * kTh;
+      out_w[b] = (float)t[0];
+      for (int j = 0; j < 4; ++j) out_mu[4 * b + j] = (float)t[1 + j];
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c)
+          out_cov[16 * b + 4 * r + c] = (float)t[5 + (r >= c ? tri(r, c) : tri(c, r))];
+    }
+    return;
+  }
+  const double N0 = tot[0];
+  double S1[4];
+  for (int j = 0; j < 4; ++j) S1[j] = tot[1 + j];
+  const float4 mf = shift_in[b];
+  const double m[4] = {mf.x, mf.y, mf.z, mf.w};
+  const double Nb = N0 + kEpsN;
+  const double rN = 1.0 / Nb;
+  double mu[4], dl[4];
+  bool fin = isfinite(N0);
+  for (int j = 0; j < 4; ++j) {
+    mu[j] = (S1[j] + N0 * m[j]) * rN;
+    dl[j] = mu[j] - m[j];
+    fin = fin && isfinite(S1[j]);
+  }
+  if (a.umode == kUpdMeanOnly) {
+    if (!fin) set_status(status, kStNonFinite);
+    shift_out[b] = make_float4((float)mu[0], (float)mu[1], (float)mu[2], (float)mu[3]);
+    for (int j = 0; j < kPar; ++j) cpar_out[(size_t)b * kPar + j] = cpar_in[(size_t)b * kPar + j];
+    if (b == 0)
+      *reinterpret_cast<double *>(cpar_out + (size_t)K * kPar) =
+          *reinterpret_cast<const double *>(cpar_in + (size_t)K * kPar);
+    return;
+  }
+  double C[10];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c <= r; ++c) {
+      const double s2 = tot[5 + tri(r, c)];
+      const double v = s2 - S1[r] * dl[c] - dl[r] * S1[c] + N0 * dl[r] * dl[c];
+      C[tri(r, c)] = v * rN + (r == c ? a.reg : 0.0);
+      fin = fin && isfinite(s2);
+    }
+  if (!fin) set_status(status, kStNonFinite);
+  float *q = cpar_out + (size_t)b * kPar;
+  const double cb = store_block4(q, mu, C, Nb);
+  if (!isfinite(cb)) set_status(status, kStNotSpd);
+  double *t = th64 + (size_t)b * kTh;
+  t[0] = Nb / a.Ntot;
+  for (int j = 0; j < 4; ++j) t[1 + j] = mu[j];
+  for (int j = 0; j < 10; ++j) t[5 + j] = C[j];
+  t[15] = Nb;
+  shift_out[b] = make_float4((float)mu[0], (float)mu[1], (float)mu[2], (float)mu[3]);
+  q[4] = isfinite(cb) ? (float)((cb - a.lnZ) * kLog2e) : -INFINITY;
+  if (b == 0) *reinterpret_cast<double *>(cpar_out + (size_t)K * kPar) = a.Chdr;
 }
 
 // Caller-supplied parameters (FP32 w, mu K x 4, cov K x 4 x 4) -> FP64 state,

@@ -176,6 +176,7 @@ struct Run4 {
   int64_t n = 0;
   const float4 *pts = nullptr;
   const int32_t *labels = nullptr;
+  bool fused = false;   // lambda > 0: one reduction + update launch per pass
 };
 
 gmm_status pass4(Run4 &r, int mode, int umode, double reg, double *slot,
@@ -188,11 +189,32 @@ gmm_status pass4(Run4 &r, int mode, int umode, double reg, double *slot,
   a.P = r.c.P;
   a.mode = mode;
   a.ncols = L.ncols;
+  const bool fuse = r.fused && reg > 0.0;
+  a.cmaj = fuse ? 1 : 0;
   r.c.launch(r.c, r.s, r.pts, r.labels, at<float>(r.ws, L.cpar[r.cur]),
              at<float4>(r.ws, L.shift[r.cur]), at<double>(r.ws, L.part), a);
   HIP_TRY(hipGetLastError());
-  const int col0 = 0;
-  (void)col0;
+  if (fuse) {
+    const int nxt = 1 - r.cur;
+    Fuse4Args fa;
+    fa.K = r.K;
+    fa.ncols = L.ncols;
+    fa.nrows = r.c.grid;
+    fa.mode = mode;
+    fa.umode = umode;
+    fa.reg = reg;
+    fa.Ntot = (double)r.n + r.K * kEpsN;
+    fa.lnZ = log(fa.Ntot) - 2.0 * log(reg) - log((double)r.K);
+    fa.Chdr = (-2.0 * log(reg) - 2.0 * kLn2Pi - log((double)r.K)) * kLog2e;
+    hipLaunchKernelGGL(reduce_update4_kernel, dim3(r.K), dim3(kFuse4Threads), 0, r.s,
+                       at<double>(r.ws, L.part), at<float>(r.ws, L.cpar[r.cur]),
+                       at<float4>(r.ws, L.shift[r.cur]), at<float>(r.ws, L.cpar[nxt]),
+                       at<float4>(r.ws, L.shift[nxt]), at<double>(r.ws, L.th64), slot, ow, omu,
+                       ocov, at<uint32_t>(r.ws, L.status), fa);
+    HIP_TRY(hipGetLastError());
+    if (umode != kUpdNone) r.cur = nxt;
+    return GMM_OK;
+  }
   hipLaunchKernelGGL(reduce4_kernel, dim3((L.ncols + 255) / 256, kRedChunks), dim3(256), 0,
                      r.s, at<double>(r.ws, L.part), r.c.grid, L.ncols, at<double>(r.ws, L.red));
   HIP_TRY(hipGetLastError());
@@ -220,6 +242,124 @@ gmm_status check_fit4(int64_t n, int32_t k) {
   if (k > kMaxK) return fail(GMM_ERR_UNSUPPORTED, "k=%d above the 4D limit %d", k, kMaxK);
   if (k > n) return fail(GMM_ERR_INVALID_ARG, "k=%d > n=%lld", k, (long long)n);
   return GMM_OK;
+}
+
+
+// The whole fit on r.s: init, checks, theta_0, T iterations, the final
+// log-likelihood pass and the outputs.
+gmm_status enqueue4(Run4 &r, float *w, float *mu, float *cov, double *loglik,
+                    const gmm_fit_opts *opts) {
+  const int k = r.K;
+  const int64_t n = r.n;
+  void *ws = r.ws;
+  gmm_status st;
+  hipLaunchKernelGGL(init4_kernel, dim3(1), dim3(256), 0, r.s, at<uint32_t>(ws, r.L.status),
+                     r.labels ? at<float4>(ws, r.L.shift[0]) : nullptr, k);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(check4_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, r.s,
+                     r.pts, r.labels, n, k, at<uint32_t>(ws, r.L.status));
+  HIP_TRY(hipGetLastError());
+  const double reg = opts->reg_covar;
+  r.cur = 0;
+  if (r.labels) {
+    // theta_0 = M-step of the one-hot responsibilities: the mean (shift 0),
+    // then the scatter about it
+    if ((st = pass4(r, kLabels, kUpdMeanOnly, reg, nullptr)) != GMM_OK) return st;
+    if ((st = pass4(r, kLabels, kUpdFull, reg, nullptr)) != GMM_OK) return st;
+  } else {
+    hipLaunchKernelGGL(precompute4_kernel, dim3(1), dim3(kUpdThreads), 0, r.s, w, mu, cov, k,
+                       at<float>(ws, r.L.cpar[0]), at<float4>(ws, r.L.shift[0]),
+                       at<double>(ws, r.L.th64), at<uint32_t>(ws, r.L.status));
+    HIP_TRY(hipGetLastError());
+  }
+  for (int t = 0; t < opts->iters; ++t) {
+    double *slot = loglik ? loglik + t : nullptr;
+    if (opts->moment_mode == GMM_MOMENTS_TWO_PASS) {
+      if ((st = pass4(r, kSoftStats, kUpdMeanOnly, reg, slot)) != GMM_OK) return st;
+      slot = nullptr;
+    }
+    if ((st = pass4(r, kSoftStats, kUpdFull, reg, slot)) != GMM_OK) return st;
+  }
+  return pass4(r, kSoftLogLik, kUpdNone, reg, loglik ? loglik + opts->iters : nullptr, w, mu,
+               cov);
+}
+
+gmm_status finish4(Run4 &r, bool sync) {
+  if (!sync) return GMM_OK;
+  uint32_t bits = 0;
+  HIP_TRY(hipMemcpyAsync(&bits, at<uint32_t>(r.ws, r.L.status), sizeof bits,
+                         hipMemcpyDeviceToHost, r.s));
+  HIP_TRY(hipStreamSynchronize(r.s));
+  return status_from_bits(bits);
+}
+
+// ---- captured fits, keyed by every argument the launches depend on
+struct Fit4Key {
+  const void *pts, *labels, *w, *mu, *cov, *loglik, *ws;
+  int64_t n;
+  size_t ws_bytes;
+  double reg;
+  int k, iters, mode, dev;
+  const void *tile;
+  bool fused;
+  bool operator==(const Fit4Key &o) const {
+    return pts == o.pts && labels == o.labels && w == o.w && mu == o.mu && cov == o.cov &&
+           loglik == o.loglik && ws == o.ws && n == o.n && ws_bytes == o.ws_bytes &&
+           reg == o.reg && k == o.k && iters == o.iters && mode == o.mode && dev == o.dev &&
+           tile == o.tile && fused == o.fused;
+  }
+};
+
+struct Graph4Entry {
+  bool used = false;
+  Fit4Key key{};
+  hipGraphExec_t exec = nullptr;
+  uint64_t stamp = 0;
+};
+
+constexpr int kGraph4Slots = 8;
+std::mutex g_graph4_mu;
+Graph4Entry g_graph4[kGraph4Slots];
+uint64_t g_graph4_clock = 0;
+
+bool graphs_enabled() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("GMM_GRAPHS");
+    v = (e && e[0] == '0') ? 0 : 1;
+  }
+  return v == 1;
+}
+
+hipStream_t capture_stream4() {
+  thread_local hipStream_t cs[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  if (!cs[dev] && hipStreamCreateWithFlags(&cs[dev], hipStreamNonBlocking) != hipSuccess)
+    cs[dev] = nullptr;
+  return cs[dev];
+}
+
+Graph4Entry *graph4_slot(const Fit4Key &key, bool *found) {
+  Graph4Entry *victim = &g_graph4[0];
+  for (auto &e : g_graph4) {
+    if (e.used && e.key == key) {
+      *found = true;
+      e.stamp = ++g_graph4_clock;
+      return &e;
+    }
+    if (!e.used || (victim->used && e.stamp < victim->stamp)) victim = &e;
+  }
+  *found = false;
+  if (victim->exec) {
+    (void)hipDeviceSynchronize();  // an evicted graph may still be running
+    (void)hipGraphExecDestroy(victim->exec);
+  }
+  *victim = Graph4Entry{};
+  victim->used = true;
+  victim->key = key;
+  victim->stamp = ++g_graph4_clock;
+  return victim;
 }
 
 }  // namespace
@@ -263,41 +403,43 @@ gmm_status gmm4_fit(const float *pts, int64_t n, int32_t k, const int32_t *init_
   r.ws = ws;
   r.pts = reinterpret_cast<const float4 *>(pts);
   r.labels = init_labels;
-  hipLaunchKernelGGL(init4_kernel, dim3(1), dim3(256), 0, r.s, at<uint32_t>(ws, r.L.status),
-                     init_labels ? at<float4>(ws, r.L.shift[0]) : nullptr, k);
-  HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(check4_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, r.s,
-                     r.pts, init_labels, n, k, at<uint32_t>(ws, r.L.status));
-  HIP_TRY(hipGetLastError());
-  const double reg = opts->reg_covar;
-  if (init_labels) {
-    // theta_0 = M-step of the one-hot responsibilities: the mean (shift 0),
-    // then the scatter about it
-    if ((st = pass4(r, kLabels, kUpdMeanOnly, reg, nullptr)) != GMM_OK) return st;
-    if ((st = pass4(r, kLabels, kUpdFull, reg, nullptr)) != GMM_OK) return st;
-  } else {
-    hipLaunchKernelGGL(precompute4_kernel, dim3(1), dim3(kUpdThreads), 0, r.s, w, mu, cov, k,
-                       at<float>(ws, r.L.cpar[0]), at<float4>(ws, r.L.shift[0]),
-                       at<double>(ws, r.L.th64), at<uint32_t>(ws, r.L.status));
-    HIP_TRY(hipGetLastError());
+  {
+    // lambda > 0: the fused reduction + M-step (GMM_FUSED=0 keeps two launches)
+    const char *e = getenv("GMM_FUSED");
+    r.fused = opts->reg_covar > 0.0 && !(e && e[0] == '0');
   }
-  for (int t = 0; t < opts->iters; ++t) {
-    double *slot = loglik ? loglik + t : nullptr;
-    if (opts->moment_mode == GMM_MOMENTS_TWO_PASS) {
-      if ((st = pass4(r, kSoftStats, kUpdMeanOnly, reg, slot)) != GMM_OK) return st;
-      slot = nullptr;
+  const bool sync = !(opts->flags & GMM_FLAG_ASYNC);
+  // repeated calls with the same arguments replay a captured graph (the
+  // first runs directly, the second captures); not with a temporary workspace
+  if (graphs_enabled() && !guard.ptr) {
+    Fit4Key key{pts, init_labels, w, mu, cov, loglik, ws, n, ws_bytes, opts->reg_covar,
+                k, opts->iters, opts->moment_mode, 0, r.c.kfn, r.fused};
+    (void)hipGetDevice(&key.dev);
+    std::lock_guard<std::mutex> lk(g_graph4_mu);
+    bool found = false;
+    Graph4Entry *e = graph4_slot(key, &found);
+    if (found && !e->exec) {
+      hipStream_t cs = capture_stream4();
+      if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        Run4 rc = r;
+        rc.s = cs;
+        gmm_status cst = enqueue4(rc, w, mu, cov, loglik, opts);
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamEndCapture(cs, &g);
+        if (cst == GMM_OK && ee == hipSuccess && g &&
+            hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0) != hipSuccess)
+          e->exec = nullptr;
+        if (g) (void)hipGraphDestroy(g);
+      }
+      (void)hipGetLastError();
     }
-    if ((st = pass4(r, kSoftStats, kUpdFull, reg, slot)) != GMM_OK) return st;
+    if (e->exec) {
+      HIP_TRY(hipGraphLaunch(e->exec, r.s));
+      return finish4(r, sync);
+    }
   }
-  if ((st = pass4(r, kSoftLogLik, kUpdNone, reg, loglik ? loglik + opts->iters : nullptr, w, mu,
-                  cov)) != GMM_OK)
-    return st;
-  if (opts->flags & GMM_FLAG_ASYNC) return GMM_OK;
-  uint32_t bits = 0;
-  HIP_TRY(hipMemcpyAsync(&bits, at<uint32_t>(ws, r.L.status), sizeof bits,
-                         hipMemcpyDeviceToHost, r.s));
-  HIP_TRY(hipStreamSynchronize(r.s));
-  return status_from_bits(bits);
+  if ((st = enqueue4(r, w, mu, cov, loglik, opts)) != GMM_OK) return st;
+  return finish4(r, sync);
 }
 
 size_t gmm4_color_conditional_workspace_size(int32_t k) {

@@ -271,3 +271,38 @@ def test_joint_sample_statistics_and_errors():
     with pytest.raises(_lib.GmmError) as ei:
         gmm.joint_dist_sample(_to(w), _to(mu), _to(bad), 10, seed=1)
     assert ei.value.status == 2
+
+
+def test_graph_replay_is_bitwise_equal_to_direct_launches():
+    """The same C-ABI call three times with the same buffers: the first runs
+    its kernels directly, the second captures them into a graph, the third
+    replays it; all three give the same bits, and L agrees with the
+    oracle's at the fit bar."""
+    import ctypes
+    _case("graph replay")
+    X = _frame4(20000, seed=4)
+    K, T = 40, 12
+    lab = _labels(X, K, 2)
+    lib = _lib.load()
+    pts = _to(X)
+    lt = _to(lab, torch.int32)
+    w = torch.empty(K, device=DEV)
+    mu = torch.empty(K, 4, device=DEV)
+    cov = torch.empty(K, 4, 4, device=DEV)
+    L = torch.empty(T + 1, dtype=torch.float64, device=DEV)
+    opts = _lib.FitOpts(T, 1e-3, 0, 0)
+    ws = torch.empty(lib.gmm4_fit_workspace_size(X.shape[0], K, ctypes.byref(opts)),
+                     dtype=torch.uint8, device=DEV)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(DEV).cuda_stream)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    outs = []
+    for _ in range(3):
+        _lib.check(lib.gmm4_fit(p(pts), X.shape[0], K, p(lt), p(w), p(mu), p(cov), p(L),
+                                ctypes.byref(opts), p(ws), ws.numel(), stream))
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy().copy() for t in (w, mu, cov, L)])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            np.testing.assert_array_equal(a, b)
+    Lr = o4.fit(X.astype(np.float64), K, 1e-3, T, labels=lab)[3]
+    assert np.abs(outs[0][3] - Lr).max() <= 1e-4 * max(np.abs(Lr).max(), X.shape[0])
