@@ -94,6 +94,7 @@ def parse():
     ap.add_argument("--no-blobs", action="store_true")
     ap.add_argument("--no-registration", action="store_true")
     ap.add_argument("--no-model4d", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true")
     ap.add_argument("--no-meanshift", action="store_true")
     ap.add_argument("--no-d2d", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -425,6 +426,54 @@ def model4d_bench(reps=5, cpu=True):
                                        "sample": "label M-step + 2 EM iterations of the same fit "
                                                  "(numpy FP64), per pass"}
         out[name] = sec
+    return out
+
+
+def pipeline_bench(reps=3):
+    """The paper's GPU pipeline end to end on the 320 x 240 depth-intensity
+    frame (76,800 4D points): mean shift for K at bandwidth h, k-means++
+    seeding of K centres on the xyz part (draws from seed 1), then the 4D EM
+    fit (T = 100, lambda = 1e-3) from those labels; bandwidths 0.2 and 0.3,
+    the smallest of the synthetic frame whose K fits the 4D fit (K <= 512).
+    Median over reps of each stage and of the whole chain."""
+    import numpy as np
+    import torch
+
+    import paper_2307_00071_amd as gmm
+    from paper_2307_00071_amd import synth
+
+    dev = torch.device("cuda:0")
+    X = np.ascontiguousarray(
+        synth.depth_intensity_frame(0).reshape(480, 640, 4)[::2, ::2].reshape(-1, 4))
+    pts = torch.from_numpy(X).to(dev)
+    xyz = pts[:, :3].contiguous()
+    N, T = X.shape[0], 100
+    msws = torch.empty(gmm.meanshift_workspace_bytes(N, 4), dtype=torch.uint8, device=dev)
+    out = {"workload": "320x240 depth-intensity frame: mean shift (K) -> k-means++ on xyz "
+                       "-> 4D EM, T=100, lambda=1e-3"}
+    for h in (0.2, 0.3):
+        stages = {"meanshift": [], "kmeanspp": [], "fit4": [], "total": []}
+        K = None
+        for rep in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, info = gmm.meanshift(pts, h, workspace=msws)
+            K = info["n_modes"]
+            t1 = time.perf_counter()
+            lab, _ = gmm.kmeanspp(xyz, K, seed=1)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            r = gmm.fit4(pts, K, iters=T, labels=lab)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            if rep == 0:
+                continue   # warm-up
+            stages["meanshift"].append(t1 - t0)
+            stages["kmeanspp"].append(t2 - t1)
+            stages["fit4"].append(t3 - t2)
+            stages["total"].append(t3 - t0)
+        out["h=%g" % h] = {"K": K, "final_loglik": float(r.loglik[-1].item()),
+                           **{k + "_ms": 1e3 * float(np.median(v)) for k, v in stages.items()}}
     return out
 
 
@@ -763,6 +812,7 @@ def main():
         ("registration", not args.no_registration, lambda: registration(cpu=cpu)),
         ("model4d", not args.no_model4d, lambda: model4d_bench(cpu=cpu)),
         ("meanshift", not args.no_meanshift, lambda: meanshift_bench(cpu=cpu)),
+        ("pipeline", not args.no_pipeline, pipeline_bench),
         ("d2d", not args.no_d2d, lambda: d2d_bench(cpu=cpu)),
     ]
     for name, on, run in sections:
