@@ -347,6 +347,27 @@ struct GridQuery {
 };
 
 // -------------------------------------------------------------- mean shift
+// Cells with at most kMsSerial points are walked by the lane that owns their
+// slot; larger cells by the whole wave (point p of a cell starting at b goes
+// to lane (p - b) mod 64), one cell after another in slot order.  Every lane
+// therefore sums its points in an order fixed by the cells alone: the mean
+// of an iterate depends only on the set of points within h of it.
+constexpr int kMsSerial = 16;
+
+template <int D>
+__device__ __forceinline__ void ms_take(const float4 &x, bool ok, const double *s, double h2,
+                                        double *acc, int &in) {
+  const double xv[4] = {(double)x.x, (double)x.y, (double)x.z, (double)x.w};
+  double d[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) d[j] = xv[j] - s[j];
+  if (ok && sq_norm<D>(d) <= h2) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) acc[j] = acc[j] + xv[j];
+    ++in;
+  }
+}
+
 // One wave per seed (a cell, in sorted order = lexicographic bin order):
 // mode, weight (the last neighbourhood's size; 0 = dropped) and the
 // iteration count of the oracle's loop.
@@ -378,21 +399,37 @@ __global__ __launch_bounds__(kMsThreads) void ms_shift_kernel(
     for (int j = 0; j < D; ++j) acc[j] = 0.0;
     int in = 0;
     for (int u0 = 0; u0 < (1 << (2 * D)); u0 += 64) {
+      int b = 0, e = 0;
       uint64_t key;
-      if (!g.slot_key(u0 + lane, &key)) continue;
-      const int id = hash_find(hk, hv, mask, key);
-      if (id < 0) continue;
-      const int p1 = cstart[id + 1];
-      for (int p = cstart[id]; p < p1; ++p) {
-        const float4 x = ptsS[p];
-        const double xv[4] = {(double)x.x, (double)x.y, (double)x.z, (double)x.w};
-        double d[D];
+      if (g.slot_key(u0 + lane, &key)) {
+        const int id = hash_find(hk, hv, mask, key);
+        if (id >= 0) {
+          b = cstart[id];
+          e = cstart[id + 1];
+        }
+      }
+      const bool wide = e - b > kMsSerial;
+      if (!wide) {
+        for (int p0 = b; p0 < e; p0 += 4) {
+          float4 x[4];
 #pragma unroll
-        for (int j = 0; j < D; ++j) d[j] = xv[j] - s[j];
-        if (sq_norm<D>(d) <= h2) {
+          for (int k = 0; k < 4; ++k) x[k] = ptsS[min(p0 + k, e - 1)];
 #pragma unroll
-          for (int j = 0; j < D; ++j) acc[j] = acc[j] + xv[j];
-          ++in;
+          for (int k = 0; k < 4; ++k) ms_take<D>(x[k], p0 + k < e, s, h2, acc, in);
+        }
+      }
+      uint64_t big = __ballot(wide);
+      while (big) {
+        const int o = __builtin_ctzll(big);
+        big &= big - 1;
+        const int cb = __builtin_amdgcn_readlane(b, o);
+        const int ce = __builtin_amdgcn_readlane(e, o);
+        for (int p0 = cb + lane; p0 < ce; p0 += 256) {
+          float4 x[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) x[k] = ptsS[min(p0 + 64 * k, ce - 1)];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) ms_take<D>(x[k], p0 + 64 * k < ce, s, h2, acc, in);
         }
       }
     }
