@@ -998,6 +998,32 @@ __device__ __forceinline__ void cull_begin(const CullLds &L, const float *__rest
   __syncthreads();
 }
 
+// The first tile's point of this lane and the first two tile spheres,
+// loaded before the LDS staging so that both memory round trips overlap.
+struct TilePre {
+  float4 x, s0, s1;
+};
+template <int BLOCK, int T, int TRIP, int SCAP, bool LAB>
+__device__ __forceinline__ TilePre tile_pre(const float4 *__restrict__ pts,
+                                            const float4 *__restrict__ sph, int first, int end,
+                                            int stride) {
+  using S = CullShape<BLOCK, T, TRIP, SCAP>;
+  const int w = threadIdx.x >> 6;
+  const int t = (w % S::W) * 64 + (threadIdx.x & 63);
+  TilePre p;
+  p.x = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+  p.s0 = make_float4(0.f, 0.f, 0.f, -1.0f);
+  p.s1 = p.s0;
+  if (first < end) {
+    p.x = pts[(size_t)first * T + t];
+    if (!LAB) {
+      p.s0 = sph[first];
+      if (first + stride < end) p.s1 = sph[first + stride];
+    }
+  }
+  return p;
+}
+
 // The tiles first, first + stride, ... < end of one frame: cull, E-phase,
 // normaliser, M-phase into L.acc; lse sums into Lacc, active pairs into
 // npairs (thread 0).
@@ -1006,7 +1032,7 @@ __device__ __forceinline__ void cull_tiles(
     const CullLds &L, const float4 *__restrict__ pts, const float4 *__restrict__ sph,
     const float *__restrict__ cpar, const float4 *__restrict__ shift, int K, int mode,
     int first, int end, int stride, float *__restrict__ lse_out, double &Lacc,
-    unsigned long long &npairs) {
+    unsigned long long &npairs, const TilePre &pre) {
   using S = CullShape<BLOCK, T, TRIP, SCAP>;
   constexpr int NW = S::NW, W = S::W, R = S::R, P = S::P, RS = S::RS;
   constexpr int SLOTS = BLOCK / P;  // slots per M round
@@ -1075,18 +1101,16 @@ __device__ __forceinline__ void cull_tiles(
   // first tile: masks, list (buffer 0); the point and sphere of the next tile
   int tile = first;
   int cur = 0;
-  float4 xn = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
-  float4 spn = make_float4(0.f, 0.f, 0.f, -1.0f);
+  float4 xn = pre.x;
+  float4 spn = pre.s1;
   if (tile < end) {
-    xn = pts[(size_t)tile * T + t];
     if constexpr (LAB) {
       mark_label(xn, masks);
     } else {
       if (w < nchk) {
-        const uint64_t m = cull_mask(sph[tile]);
+        const uint64_t m = cull_mask(pre.s0);
         if (lane == 0) masks[w] = m;
       }
-      if (tile + stride < end) spn = sph[tile + stride];
     }
   }
   __syncthreads();
@@ -1348,14 +1372,18 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_kernel(
     float *__restrict__ lse_out,       // N or NULL
     TileArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  if (a.conv && (*a.conv & 1u)) return;   // converged fit: nothing to do
+  // the flag, the first tile and the staged parameters are all requested
+  // before the first wait; a converged fit returns before writing anything
+  const bool done = a.conv && (*a.conv & 1u);
+  const TilePre pre = tile_pre<BLOCK, T, TRIP, SCAP, LAB>(pts, sph, blockIdx.x, a.ntiles, gridDim.x);
   const CullLds L = cull_carve<BLOCK, T, TRIP, SCAP, CPR>(smem, a.K);
   cull_begin<BLOCK, CPR>(L, cpar, shift, a.K);
+  if (done) return;   // uniform over the block, after cull_begin's barrier
   double Lacc = 0.0;
   unsigned long long npairs = 0;
   cull_tiles<BLOCK, T, TRIP, SCAP, CPR, LAB, MEANS>(L, pts, sph, cpar, shift, a.K, a.mode,
                                                    blockIdx.x, a.ntiles, gridDim.x, lse_out,
-                                                   Lacc, npairs);
+                                                   Lacc, npairs, pre);
   cull_end<BLOCK>(L, part + (size_t)blockIdx.x * a.ncols, a.K, a.mode, Lacc, a.cmaj != 0);
   if (threadIdx.x == 0 && a.pairs) atomicAdd(a.pairs, npairs);
 }
@@ -1735,11 +1763,12 @@ __attribute__((amdgpu_waves_per_eu(GMM_CULL_WPE, 8))) void em_cull_batch_kernel(
     const BSeg g = segs[si];
     const BFrame F = frames[g.frame];
     const float *cpar = cpar_all + F.cpoff;
+    const TilePre pre = tile_pre<BLOCK, T, TRIP, SCAP, false>(pts, sph, g.t0, g.t1, 1);
     cull_begin<BLOCK, false>(L, cpar, shift_all + F.koff, F.K);
     double Lacc = 0.0;
     unsigned long long npairs = 0;
     cull_tiles<BLOCK, T, TRIP, SCAP, false, false>(L, pts, sph, cpar, shift_all + F.koff, F.K,
-                                             mode, g.t0, g.t1, 1, nullptr, Lacc, npairs);
+                                             mode, g.t0, g.t1, 1, nullptr, Lacc, npairs, pre);
     cull_end<BLOCK>(L, part + F.poff + (size_t)g.row * F.ncols, F.K, mode, Lacc);
   }
 }
