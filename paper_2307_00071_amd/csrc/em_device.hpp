@@ -889,6 +889,43 @@ __device__ __forceinline__ void subset_sum(float *a) {
   }
 }
 
+// Ten statistics summed over the 16 adjacent lanes of a slot as a
+// reduce-scatter: each exchange keeps only the statistics that this lane's
+// side of the pair will own, so lane q ends with the total of statistic
+// scatter_stat(q) (-1: none). Exchanges: mirror (q, 15 - q) keeps 0-4 in
+// the low half and 5-9 in the high half; half-mirror (q, 7 - q) keeps the
+// first three / last two of those; then q ^ 2 and q ^ 1.
+__device__ __forceinline__ int scatter_stat(int q) {
+  const int r = q & 7, h = (q >> 3) * 5;
+  return r < 3 ? h + r : (r == 4 || r == 5) ? h + r - 1 : -1;
+}
+__device__ __forceinline__ float dpp_from_mirror(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_from_half_mirror(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_from_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float scatter_sum16(const float *a, int q) {
+  const bool hi = (q & 8) != 0, b4 = (q & 4) != 0, b2 = (q & 2) != 0, b1 = (q & 1) != 0;
+  float k[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const float keep = hi ? a[j + 5] : a[j];
+    const float send = hi ? a[j] : a[j + 5];
+    k[j] = keep + dpp_from_mirror(send);
+  }
+  const float v0 = (b4 ? k[3] : k[0]) + dpp_from_half_mirror(b4 ? k[0] : k[3]);
+  const float v1 = (b4 ? k[4] : k[1]) + dpp_from_half_mirror(b4 ? k[1] : k[4]);
+  const float v2 = dpp_add_half_mirror(k[2]);
+  const float w0 = dpp_add_xor2(v0), w1 = dpp_add_xor2(v1), w2 = dpp_add_xor2(v2);
+  const float keep = b2 ? w2 : (b1 ? w1 : w0);
+  const float send = b2 ? w2 : (b1 ? w0 : w1);
+  return keep + dpp_from_xor1(send);
+}
+
 // Cull parameters of one component: (mu, c'), (P'0..3), (P'4, P'5, |P'|_F);
 // c' = -inf for a lane past the last component.
 struct CullPar {
@@ -1272,14 +1309,20 @@ __device__ __forceinline__ void cull_tiles(
             }
             // MEANS: the first pass of two-pass moments needs N and S1 only
             constexpr int NS = MEANS ? 4 : kNStat;
-            subset_sum<P, NS>(av);
-            // lane q adds statistic q (and q + 8 when P = 8)
-            float u0 = av[0];
-#pragma unroll
-            for (int j = 1; j < NS; ++j) u0 = (q == j) ? av[j] : u0;
             double *ab = acc + (size_t)b * kNStat;
-            if (q < NS) ab[q] += (double)u0;
-            if (!MEANS && P == 8 && q < 2) ab[q + 8] += (double)(q == 0 ? av[8] : av[9]);
+            if constexpr (P == 16 && NS == kNStat) {
+              const float u0 = scatter_sum16(av, q);
+              const int st = scatter_stat(q);
+              if (st >= 0) ab[st] += (double)u0;
+            } else {
+              subset_sum<P, NS>(av);
+              // lane q adds statistic q (and q + 8 when P = 8)
+              float u0 = av[0];
+#pragma unroll
+              for (int j = 1; j < NS; ++j) u0 = (q == j) ? av[j] : u0;
+              if (q < NS) ab[q] += (double)u0;
+              if (!MEANS && P == 8 && q < 2) ab[q + 8] += (double)(q == 0 ? av[8] : av[9]);
+            }
           }
         }
       }
