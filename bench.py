@@ -71,9 +71,9 @@ PROFILE_REPS = 16           # tile launches per timed event pair
 # 256 MiB device copy (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all
 # of them).  Valid only for the kernel source and tile shape it was taken
 # on: any other reports null.
-TRAFFIC = {"kernel_src_sha256": "5252fa387e6db96505470bdbee8eee80d5626fd10a7665e91dd7c56388ed408e",
+TRAFFIC = {"kernel_src_sha256": "726a62c8e91a43f243252903b15e4a4a4fd416828cb77c2ca9aed4a4cf6bf5f2",
            "tile_shape": "c512t128p16", "N": 307200, "K": 100,
-           "fetch_kib": 2671.59, "fetch_factor": 2.0,
+           "fetch_kib": 2668.11, "fetch_factor": 2.0,
            "write_kib": 6044.21, "write_factor": 1.0}
 
 
@@ -481,7 +481,8 @@ def meanshift_bench(reps=5, cpu=True, cpu_seeds=60):
     """Component count by mean shift on the 4D depth-intensity frame at the
     paper's 2x-reduced image size (320 x 240 = 76,800 points, every other
     pixel of the synthetic 640 x 480 frame), bandwidths 0.015 (the paper's
-    example) and 0.03; median of reps whole calls.  The CPU baseline is the
+    example), 0.03 and 0.1 (larger neighbourhoods, K ~ 2,300); median of
+    reps whole calls.  The CPU baseline is the
     FP64 oracle's per-seed mean shift on a seeded sample of the seeds,
     scaled to seeds per second (the merge is not timed there)."""
     import numpy as np
@@ -498,7 +499,7 @@ def meanshift_bench(reps=5, cpu=True, cpu_seeds=60):
                      device=dev)
     out = {"workload": "320x240 depth-intensity frame (N=76800, 4D), flat-kernel mean "
                        "shift over binned seeds, max_iter=300"}
-    for h in (0.015, 0.03):
+    for h in (0.015, 0.03, 0.1):
         gmm.meanshift(pts, h, workspace=ws)
         torch.cuda.synchronize()
         times = []
