@@ -285,8 +285,12 @@ gmm_status gmm_kmeanspp(const float *pts, int64_t n, int32_t k, const double *u,
  * D = 4 (eq. 1-3 with D ln 2pi / 2 = 2 ln 2pi; M-step N_b = sum g + 10
  * DBL_EPSILON, pi_b = N_b / sum N, mu_b = sum g x / N_b, Sigma_b = sum g
  * (x - mu)(x - mu)^T / N_b + lambda I; FP32 E-step, FP64 sums, FP64 4 x 4
- * Cholesky).  Every tile of 64 points is evaluated against every component
- * (no spatial ordering or skipping).
+ * Cholesky).  The soft passes take the points in Morton order of their
+ * xyz part (a copy in the workspace) and skip the (64-point tile,
+ * component) pairs whose FP32 weight is zero for the whole tile, bounded by
+ * the xyz marginal of the component; the result is the dense evaluation's
+ * up to the order of floating-point additions.  GMM_CULL4=0 evaluates every
+ * pair in the caller's order; the workspace size depends on that setting.
  *  pts          device float32 N x 4 (x, y, z, intensity), 16-byte aligned.
  *  init_labels  device int32 N in [0, K), or NULL (then w/mu/cov hold
  *               theta_0 on entry, weights used as given).

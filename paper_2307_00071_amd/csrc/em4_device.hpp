@@ -774,4 +774,439 @@ __global__ __launch_bounds__(256) void sample4_kernel(
   if (comp) comp[i] = b;
 }
 
+// ------------------------------------------------------- culled passes
+// A soft pass that skips the (tile, component) pairs whose FP32 weight is
+// exactly zero for every point of the tile, as the 3D culled kernel does.
+// The first three rows of the lower-triangular P' involve x, y, z only, so
+// |P'(x - mu)|^2 >= |P'_3 (x_3 - mu_3)|^2 with P'_3 its leading 3 x 3 block
+// (the xyz marginal's factor), and for every point whose xyz part lies in a
+// sphere (c, r): |P'_3 (x_3 - mu_3)| >= |P'_3 (c - mu_3)| - |P'_3|_F r.
+// Where c'_b - max(0, that)^2 is below kCull4Log2 (two units under the
+// smallest FP32 subnormal exponent) every e_pb of the tile rounds to zero;
+// skipping the pair changes nothing beyond the order of FP32 additions.
+// Tiles are 64 points of a cloud in Morton order of its xyz part.
+constexpr float kCull4Log2 = -152.0f;
+constexpr int kOrd = 256;            // threads of the ordering kernels
+constexpr int kBox4Blocks = 256;
+constexpr int kCull4Cap = 128;       // E rows kept per tile at most
+constexpr int kCull4Waves = 8;       // waves per block (16 measured no faster at K = 505)
+
+__device__ inline void box4_reduce(float *lo, float *hi, float *sh /* 4 x 6 */) {
+  for (int off = 32; off > 0; off >>= 1)
+    for (int j = 0; j < 3; ++j) {
+      lo[j] = fminf(lo[j], __shfl_xor(lo[j], off, 64));
+      hi[j] = fmaxf(hi[j], __shfl_xor(hi[j], off, 64));
+    }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int j = 0; j < 3; ++j) {
+      sh[w * 6 + j] = lo[j];
+      sh[w * 6 + 3 + j] = hi[j];
+    }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int v = 1; v < kOrd / 64; ++v)
+      for (int j = 0; j < 3; ++j) {
+        lo[j] = fminf(lo[j], sh[v * 6 + j]);
+        hi[j] = fmaxf(hi[j], sh[v * 6 + 3 + j]);
+      }
+}
+
+// Partial xyz boxes of the n points: part6[block] = (lo, hi).
+__global__ __launch_bounds__(kOrd) void bbox4_kernel(const float4 *__restrict__ pts, int64_t n,
+                                                     float *__restrict__ part6) {
+  __shared__ float sh[kOrd / 64 * 6];
+  float lo[3] = {INFINITY, INFINITY, INFINITY};
+  float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = (int64_t)blockIdx.x * kOrd + threadIdx.x; i < n; i += (int64_t)gridDim.x * kOrd) {
+    const float4 x = pts[i];
+    lo[0] = fminf(lo[0], x.x); lo[1] = fminf(lo[1], x.y); lo[2] = fminf(lo[2], x.z);
+    hi[0] = fmaxf(hi[0], x.x); hi[1] = fmaxf(hi[1], x.y); hi[2] = fmaxf(hi[2], x.z);
+  }
+  box4_reduce(lo, hi, sh);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 3; ++j) {
+      part6[blockIdx.x * 6 + j] = lo[j];
+      part6[blockIdx.x * 6 + 3 + j] = hi[j];
+    }
+}
+
+__device__ inline unsigned spread3_4(unsigned v) {
+  v &= 0xFFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// keys[i] = Morton code of the xyz part of point i in a cubic 256^3 grid
+// over the box (0xFFFFFF past the last point, so padding sorts last);
+// vals[i] = i.
+__global__ __launch_bounds__(kOrd) void morton4_kernel(
+    const float4 *__restrict__ pts, int64_t n, int64_t npad, const float *__restrict__ part6,
+    int nbox, unsigned *__restrict__ keys, unsigned *__restrict__ vals) {
+  __shared__ float sh[kOrd / 64 * 6];
+  __shared__ float box[4];
+  float lo[3] = {INFINITY, INFINITY, INFINITY};
+  float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = threadIdx.x; b < nbox; b += kOrd)
+    for (int j = 0; j < 3; ++j) {
+      lo[j] = fminf(lo[j], part6[b * 6 + j]);
+      hi[j] = fmaxf(hi[j], part6[b * 6 + 3 + j]);
+    }
+  box4_reduce(lo, hi, sh);
+  if (threadIdx.x == 0) {
+    const float ext = fmaxf(fmaxf(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
+    box[0] = lo[0];
+    box[1] = lo[1];
+    box[2] = lo[2];
+    box[3] = (ext > 0.0f && ext < INFINITY) ? 255.99f / ext : 0.0f;
+  }
+  __syncthreads();
+  const float l0 = box[0], l1 = box[1], l2 = box[2], sc = box[3];
+  for (int64_t i = (int64_t)blockIdx.x * kOrd + threadIdx.x; i < npad;
+       i += (int64_t)gridDim.x * kOrd) {
+    unsigned key = 0xFFFFFFu;
+    if (i < n) {
+      const float4 x = pts[i];
+      const unsigned q0 = (unsigned)fminf(fmaxf((x.x - l0) * sc, 0.0f), 255.0f);
+      const unsigned q1 = (unsigned)fminf(fmaxf((x.y - l1) * sc, 0.0f), 255.0f);
+      const unsigned q2 = (unsigned)fminf(fmaxf((x.z - l2) * sc, 0.0f), 255.0f);
+      key = spread3_4(q0) | (spread3_4(q1) << 1) | (spread3_4(q2) << 2);
+    }
+    keys[i] = key;
+    vals[i] = (unsigned)i;
+  }
+}
+
+// out[i] = in[perm[i]] (zero past the n points), labels likewise.
+__global__ __launch_bounds__(kOrd) void gather4_kernel(
+    const float4 *__restrict__ in, const int32_t *__restrict__ lab_in,
+    const unsigned *__restrict__ perm, int64_t n, int64_t npad, float4 *__restrict__ out,
+    int32_t *__restrict__ lab_out) {
+  const int64_t i = (int64_t)blockIdx.x * kOrd + threadIdx.x;
+  if (i >= npad) return;
+  const int64_t j = perm[i];
+  out[i] = j < n ? in[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+  if (lab_out) lab_out[i] = (lab_in && j < n) ? lab_in[j] : 0;
+}
+
+// Bounding sphere (xyz centre, radius) of every 64-point tile of the
+// ordered points, radius -1 when the tile holds no finite point.  One wave
+// per tile.
+__global__ __launch_bounds__(kOrd) void tile_sphere4_kernel(const float4 *__restrict__ pts,
+                                                            int64_t n, int ntiles,
+                                                            float4 *__restrict__ sph) {
+  const int t = blockIdx.x * (kOrd / 64) + (threadIdx.x >> 6);
+  if (t >= ntiles) return;   // uniform per wave
+  const int64_t i = (int64_t)t * kT + (threadIdx.x & 63);
+  float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+  bool ok = false;
+  if (i < n) {
+    x = pts[i];
+    ok = isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(x.w);
+  }
+  float lo0 = ok ? x.x : INFINITY, lo1 = ok ? x.y : INFINITY, lo2 = ok ? x.z : INFINITY;
+  float hi0 = ok ? x.x : -INFINITY, hi1 = ok ? x.y : -INFINITY, hi2 = ok ? x.z : -INFINITY;
+  for (int off = 32; off > 0; off >>= 1) {
+    lo0 = fminf(lo0, __shfl_xor(lo0, off, 64));
+    lo1 = fminf(lo1, __shfl_xor(lo1, off, 64));
+    lo2 = fminf(lo2, __shfl_xor(lo2, off, 64));
+    hi0 = fmaxf(hi0, __shfl_xor(hi0, off, 64));
+    hi1 = fmaxf(hi1, __shfl_xor(hi1, off, 64));
+    hi2 = fmaxf(hi2, __shfl_xor(hi2, off, 64));
+  }
+  if ((threadIdx.x & 63) != 0) return;
+  if (!(lo0 <= hi0)) {
+    sph[t] = make_float4(0.f, 0.f, 0.f, -1.0f);
+    return;
+  }
+  const float c0 = 0.5f * (lo0 + hi0), c1 = 0.5f * (lo1 + hi1), c2 = 0.5f * (lo2 + hi2);
+  const float e0 = hi0 - lo0, e1 = hi1 - lo1, e2 = hi2 - lo2;
+  // half diagonal, widened for the rounding of the centre and the norm
+  const float scale = fmaxf(fmaxf(fabsf(c0), fabsf(c1)), fabsf(c2)) + 1.0f;
+  const float r = 0.5f * sqrtf(e0 * e0 + e1 * e1 + e2 * e2) * (1.0f + 1e-5f) + 1e-5f * scale;
+  sph[t] = make_float4(c0, c1, c2, r);
+}
+
+struct Cull4Args {
+  int64_t n;
+  int ntiles, K, mode, ncols, scap;
+  int cmaj;   // partial row component-major (b kNStat + j), for the fused update
+};
+
+// LDS of the culled kernel: FP64 sums (K x kNStat) | E rows (scap x kTS) |
+// Xs (kT float4) | Rs (kT) | partial normalisers (8 x kT) | far-point
+// (max, sum) (kT float2) | per-wave chunk lists (8 x 64 uint16) | slot ->
+// component (kMaxK uint16) | chunk counts (8) | far-point mask | wL (8).
+struct Cull4Lds {
+  size_t acc, E, Xs, Rs, reds, fbv, lst, comp, cnt, fbm, wL, total;
+};
+__host__ __device__ inline Cull4Lds cull4_lds(int K, int scap, int nw) {
+  Cull4Lds L{};
+  size_t o = 0;
+  auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
+  L.acc = o; o = al(o + (size_t)K * kNStat * sizeof(double));
+  L.E = o; o = al(o + (size_t)scap * kTS * sizeof(float));
+  L.Xs = o; o = al(o + kT * sizeof(float4));
+  L.Rs = o; o = al(o + kT * sizeof(float));
+  L.reds = o; o = al(o + (size_t)nw * kT * sizeof(float));
+  L.fbv = o; o = al(o + kT * sizeof(float2));
+  L.lst = o; o = al(o + (size_t)nw * 64 * sizeof(uint16_t));
+  L.comp = o; o = al(o + kMaxK * sizeof(uint16_t));
+  L.cnt = o; o = al(o + (size_t)nw * sizeof(int));
+  L.fbm = o; o = al(o + sizeof(unsigned long long));
+  L.wL = o; o = al(o + (size_t)nw * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+// One culled soft pass (E+M statistics, or L only), grid-strided over the
+// 64-point tiles, NW waves per block.  Per tile, four barriers:
+//  cull    wave g < ceil(K / 64) tests components 64 g .. 64 g + 63
+//          (parameters held in registers for the whole launch) against the
+//          tile's sphere and writes its active components, in order, to its
+//          own chunk list |
+//  E-phase the active components taken in chunk order form slots 0 ..
+//          nact - 1; wave g takes slots g, g + NW, ... for the tile's 64
+//          points and stores e_pb in LDS row `slot` (rows for scap slots;
+//          later rows are recomputed in the M-phase chunk by chunk) |
+//  normaliser  wave 0, one lane per point: s_p, 1 / s_p and L; a point
+//          with s_p below 2^-100 is left out and added after the M-phase
+//          with its own maximum over all K components, as the dense kernel
+//          does (one more round over every component, 1 / s_p of those
+//          points only) |
+//  M-phase lanes = (slot, subset of 8 points): FP32 statistics, summed over
+//          the 8 subsets by DPP in a fixed order, added to the FP64 sums.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void em4_cull_kernel(
+    const float4 *__restrict__ pts, const float4 *__restrict__ sph,
+    const float *__restrict__ cpar, const float4 *__restrict__ shift,
+    double *__restrict__ part, Cull4Args a) {
+  constexpr int G = NW, BLOCK = NW * 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int K = a.K, mode = a.mode, scap = a.scap;
+  const Cull4Lds LL = cull4_lds(K, scap, NW);
+  double *acc = reinterpret_cast<double *>(smem + LL.acc);
+  float *E = reinterpret_cast<float *>(smem + LL.E);
+  float4 *Xs = reinterpret_cast<float4 *>(smem + LL.Xs);
+  float *Rs = reinterpret_cast<float *>(smem + LL.Rs);
+  float *reds = reinterpret_cast<float *>(smem + LL.reds);
+  float2 *fbv = reinterpret_cast<float2 *>(smem + LL.fbv);
+  uint16_t *lst = reinterpret_cast<uint16_t *>(smem + LL.lst);
+  uint16_t *comp = reinterpret_cast<uint16_t *>(smem + LL.comp);
+  int *cnt = reinterpret_cast<int *>(smem + LL.cnt);
+  unsigned long long *fbm = reinterpret_cast<unsigned long long *>(smem + LL.fbm);
+  double *wL = reinterpret_cast<double *>(smem + LL.wL);
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int g = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const double Cb = *reinterpret_cast<const double *>(cpar + (size_t)K * kPar);
+  // cull parameters of component 64 g + lane: mu_xyz, c', P'_3, |P'_3|_F
+  const int cb = g * 64 + lane;
+  float m0 = 0.f, m1 = 0.f, m2 = 0.f, cc = -INFINITY;
+  float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f, p5 = 0.f, fro = 0.f;
+  if (cb < K) {
+    const float *q = cpar + (size_t)cb * kPar;
+    m0 = q[0]; m1 = q[1]; m2 = q[2]; cc = q[4];
+    p0 = q[5]; p1 = q[6]; p2 = q[7]; p3 = q[8]; p4 = q[9]; p5 = q[10];
+    fro = sqrtf(p0 * p0 + p1 * p1 + p2 * p2 + p3 * p3 + p4 * p4 + p5 * p5);
+  }
+  for (int i = tid; i < K * kNStat; i += BLOCK) acc[i] = 0.0;
+  double Lacc = 0.0;
+  __syncthreads();
+
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const int64_t idx = (int64_t)tile * kT + lane;
+    float4 x = idx < a.n ? pts[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool valid = idx < a.n && isfinite(x.x) && isfinite(x.y) && isfinite(x.z) &&
+                       isfinite(x.w);
+    if (!valid) x = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 sp = sph[tile];
+    // ---- cull: this wave's chunk of components
+    bool keep = false;
+    if (g * 64 < K && sp.w >= 0.0f) {
+      const float d0 = sp.x - m0, d1 = sp.y - m1, d2 = sp.z - m2;
+      const float z0 = p0 * d0;
+      const float z1 = fmaf(p1, d0, p2 * d1);
+      const float z2 = fmaf(p3, d0, fmaf(p4, d1, p5 * d2));
+      const float dist = sqrtf(fmaf(z0, z0, fmaf(z1, z1, z2 * z2)));
+      const float bnd = fmaxf(dist - fro * sp.w, 0.0f);
+      keep = fmaf(-bnd, bnd, cc) >= kCull4Log2;
+    }
+    const uint64_t km = __ballot(keep);
+    if (keep) {
+      const unsigned below = __builtin_amdgcn_mbcnt_hi(
+          (unsigned)(km >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)km, 0u));
+      lst[g * 64 + (int)below] = (uint16_t)cb;
+    }
+    if (lane == 0) cnt[g] = __popcll(km);
+    __syncthreads();                                                  // 1
+
+    // ---- slots: the chunk lists one after another
+    int pre[G + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int j = 0; j < G; ++j) pre[j + 1] = pre[j] + __builtin_amdgcn_readfirstlane(cnt[j]);
+    const int nact = pre[G];
+    float s = 0.0f;
+    for (int r = g; r < nact; r += G) {
+      int base = 0, off = 0;
+#pragma unroll
+      for (int j = 1; j < G; ++j)
+        if (r >= pre[j]) {
+          base = j * 64;
+          off = pre[j];
+        }
+      const int b = __builtin_amdgcn_readfirstlane((int)lst[base + r - off]);
+      const float e = __builtin_amdgcn_exp2f(logterm4(cpar + (size_t)b * kPar, x));
+      s += e;
+      if (r < scap) E[r * kTS + lane] = e;
+      if (lane == 0) comp[r] = (uint16_t)b;
+    }
+    reds[g * kT + lane] = s;
+    __syncthreads();                                                  // 2
+
+    // ---- normaliser (wave 0)
+    if (g == 0) {
+      float st = reds[lane];
+#pragma unroll
+      for (int j = 1; j < G; ++j) st += reds[j * kT + lane];
+      const bool fb = valid && !(st >= 0x1p-100f);
+      float mref = 0.0f;
+      if (fb) {
+        float mx = -INFINITY;
+        for (int bb = 0; bb < K; ++bb) mx = fmaxf(mx, logterm4(cpar + (size_t)bb * kPar, x));
+        st = 0.0f;
+        for (int bb = 0; bb < K; ++bb)
+          st += __builtin_amdgcn_exp2f(logterm4(cpar + (size_t)bb * kPar, x) - mx);
+        mref = mx;
+        fbv[lane] = make_float2(mx, st);
+      }
+      Xs[lane] = x;
+      Rs[lane] = (valid && !fb) ? __builtin_amdgcn_rcpf(st) : 0.0f;
+      const uint64_t fm = __ballot(fb);
+      if (lane == 0) *fbm = fm;
+      if (valid) Lacc += (Cb + (double)mref + (double)__builtin_amdgcn_logf(st)) * kLn2;
+    }
+    __syncthreads();                                                  // 3
+
+    // ---- M-phase
+    const uint64_t fmask = *fbm;
+    // E rows of slots [c0, c0 + nloc), the normaliser being known; far:
+    // slot = component, e = 2^(l - m_p) for the far points (max m_p)
+    auto rows = [&](int c0, int nloc, bool far) {
+      for (int u = tid; u < nloc * kT; u += BLOCK) {
+        const int sl = u >> 6, p2 = u & 63;
+        const int b = far ? c0 + sl : comp[c0 + sl];
+        const float off = (far && ((fmask >> p2) & 1ull)) ? fbv[p2].x : 0.0f;
+        E[sl * kTS + p2] =
+            __builtin_amdgcn_exp2f(logterm4(cpar + (size_t)b * kPar, Xs[p2]) - off);
+      }
+    };
+    // statistics of slots [c0, c0 + nloc) from rows 0 .. nloc - 1
+    auto stats = [&](int c0, int nloc, bool far) {
+      const int q = tid & 7;
+      for (int s0 = 0; s0 < nloc; s0 += BLOCK / 8) {
+        const int sl = s0 + (tid >> 3);
+        if (sl < nloc) {
+          const int b = far ? c0 + sl : comp[c0 + sl];
+          const float4 sh = shift[b];
+          const float *Eb = E + sl * kTS + q * 8;
+          const float4 *Xb = Xs + q * 8;
+          const float *Rb = Rs + q * 8;
+          float v[kNStat];
+#pragma unroll
+          for (int j = 0; j < kNStat; ++j) v[j] = 0.0f;
+#pragma unroll 2
+          for (int j = 0; j < 8; ++j) {
+            const float4 xr = Xb[j];
+            const float gm = Eb[j] * Rb[j];
+            const float d[4] = {xr.x - sh.x, xr.y - sh.y, xr.z - sh.z, xr.w - sh.w};
+            v[0] += gm;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const float wr = gm * d[r];
+              v[1 + r] += wr;
+#pragma unroll
+              for (int c = 0; c <= r; ++c) v[5 + tri(r, c)] = fmaf(wr, d[c], v[5 + tri(r, c)]);
+            }
+          }
+          // sum over the slot's 8 lanes as a reduce-scatter: each exchange
+          // (lane 7 - l of the half row, then l ^ 2, then l ^ 1) keeps the
+          // half of the statistics that this side owns; lane q ends with
+          // statistics 2q and 2q + 1 (statistic 15 is padding)
+          const bool b4 = (q & 4) != 0, b2 = (q & 2) != 0, b1 = (q & 1) != 0;
+          float k8[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float hi = (j + 8 < kNStat) ? v[j + 8] : 0.0f;
+            const float keep = b4 ? hi : v[j], send = b4 ? v[j] : hi;
+            k8[j] = keep + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(send), 0x141,
+                                                                   0xF, 0xF, true));
+          }
+          float k4[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float keep = b2 ? k8[j + 4] : k8[j], send = b2 ? k8[j] : k8[j + 4];
+            k4[j] = keep + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(send), 0x4E,
+                                                                   0xF, 0xF, true));
+          }
+          float k2[2];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const float keep = b1 ? k4[j + 2] : k4[j], send = b1 ? k4[j] : k4[j + 2];
+            k2[j] = keep + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(send), 0xB1,
+                                                                   0xF, 0xF, true));
+          }
+          double *ab = acc + (size_t)b * kNStat;
+          ab[2 * q] += (double)k2[0];
+          if (2 * q + 1 < kNStat) ab[2 * q + 1] += (double)k2[1];
+        }
+      }
+    };
+    if (mode != kSoftLogLik) {
+      // rounds of scap slots: the active components, then (rare) every
+      // component once more for the far points, 1 / s_p of those only
+      const int nnorm = (nact + scap - 1) / scap;
+      const int nrd = nnorm + (fmask != 0ull ? (K + scap - 1) / scap : 0);
+      for (int rd = 0; rd < nrd; ++rd) {
+        const bool far = rd >= nnorm;
+        const int c0 = (far ? rd - nnorm : rd) * scap;
+        const int nloc = min(scap, (far ? K : nact) - c0);
+        if (rd > 0 || far) {
+          if (rd > 0) __syncthreads();   // the previous rows and Rs consumed
+          if (far && rd == nnorm && g == 0)
+            Rs[lane] = ((fmask >> lane) & 1ull) ? __builtin_amdgcn_rcpf(fbv[lane].y) : 0.0f;
+          rows(c0, nloc, far);
+          __syncthreads();
+        }
+        stats(c0, nloc, far);
+      }
+    }
+    __syncthreads();                                                  // 4
+  }
+
+  double *row = part + (size_t)blockIdx.x * a.ncols;
+  if (mode != kSoftLogLik) {
+    if (a.cmaj) {
+      for (int i = tid; i < K * kNStat; i += BLOCK) row[i] = acc[i];
+    } else {
+      for (int i = tid; i < K * kNStat; i += BLOCK) {
+        const int j = i / K, b = i - j * K;
+        row[i] = acc[(size_t)b * kNStat + j];
+      }
+    }
+  }
+  double v = Lacc;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) wL[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int j = 0; j < G; ++j) sum += wL[j];
+    row[kNStat * K] = sum;
+  }
+}
+
 }  // namespace gmm4_dev

@@ -15,6 +15,7 @@
 
 #include "em4_device.hpp"
 #include "gmm.h"
+#include "radix_device.hpp"
 
 namespace gmm_host {
 extern thread_local char g_err[512];
@@ -146,12 +147,57 @@ bool make_cfg4(int K, int64_t n, Cfg4 *c) {
   return true;
 }
 
+// Culled soft passes (em4_cull_kernel) over the points in Morton order of
+// their xyz part; GMM_CULL4=0 keeps the dense kernel for every pass.
+struct CullCfg4 {
+  bool on = false;
+  int grid = 0, scap = 0, nw = 0;
+  size_t lds = 0;
+  const void *kfn = nullptr;
+};
+
+bool cull4_enabled() {
+  const char *e = getenv("GMM_CULL4");
+  return !(e && e[0] == '0');
+}
+
+bool make_cull4(int K, int64_t n, CullCfg4 *c) {
+  const int cus = device_cus();
+  if (cus <= 0 || K < 1 || K > kMaxK) return false;
+  c->scap = std::min(K, kCull4Cap);
+  c->nw = kCull4Waves;
+  c->lds = cull4_lds(K, c->scap, c->nw).total;
+  c->kfn = reinterpret_cast<const void *>(&em4_cull_kernel<kCull4Waves>);
+  if (c->lds > 65536 &&
+      hipFuncSetAttribute(c->kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds) !=
+          hipSuccess)
+    return false;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c->kfn, c->nw * 64, c->lds) !=
+          hipSuccess || per_cu <= 0)
+    return false;
+  const int64_t ntiles = (n + kT - 1) / kT;
+  c->grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, (int64_t)cus * per_cu));
+  // GMM_CULL4_GRID=<blocks>: fewer persistent blocks (tuning experiments)
+  if (const char *g = getenv("GMM_CULL4_GRID")) {
+    const int v = atoi(g);
+    if (v > 0 && v < c->grid) c->grid = v;
+  }
+  c->on = true;
+  return true;
+}
+
 struct Layout4 {
   size_t status, cpar[2], shift[2], th64, red, part, total;
   int ncols;
+  // culled passes: ordered points and labels, tile spheres, sort buffers
+  size_t spts = 0, slab = 0, tsph = 0, keys[2] = {0, 0}, vals[2] = {0, 0}, hist = 0,
+         dtot = 0, box6 = 0;
+  int64_t npad = 0;
+  int nblk = 0;
 };
 
-Layout4 layout4(int K, int grid) {
+Layout4 layout4(int K, int grid, int64_t n = 0, bool cull = false) {
   Layout4 L{};
   size_t o = 0;
   L.ncols = kNStat * K + 1;
@@ -163,12 +209,27 @@ Layout4 layout4(int K, int grid) {
   L.th64 = o; o = align256(o + (size_t)K * kTh * sizeof(double));
   L.red = o; o = align256(o + (size_t)kRedChunks * L.ncols * sizeof(double));
   L.part = o; o = align256(o + (size_t)grid * L.ncols * sizeof(double));
+  if (cull) {
+    L.npad = ((n + kT - 1) / kT) * kT;
+    L.nblk = (int)((L.npad + gmm_dev::kSortChunk - 1) / gmm_dev::kSortChunk);
+    L.spts = o; o = align256(o + (size_t)L.npad * sizeof(float4));
+    L.slab = o; o = align256(o + (size_t)L.npad * sizeof(int32_t));
+    L.tsph = o; o = align256(o + (size_t)(L.npad / kT) * sizeof(float4));
+    for (int i = 0; i < 2; ++i) {
+      L.keys[i] = o; o = align256(o + (size_t)L.npad * sizeof(unsigned));
+      L.vals[i] = o; o = align256(o + (size_t)L.npad * sizeof(unsigned));
+    }
+    L.hist = o; o = align256(o + (size_t)256 * L.nblk * sizeof(unsigned));
+    L.dtot = o; o = align256(o + 256 * sizeof(unsigned));
+    L.box6 = o; o = align256(o + (size_t)kBox4Blocks * 6 * sizeof(float));
+  }
   L.total = o;
   return L;
 }
 
 struct Run4 {
   Cfg4 c;
+  CullCfg4 cc;
   Layout4 L;
   void *ws = nullptr;
   hipStream_t s = nullptr;
@@ -191,15 +252,32 @@ gmm_status pass4(Run4 &r, int mode, int umode, double reg, double *slot,
   a.ncols = L.ncols;
   const bool fuse = r.fused && reg > 0.0;
   a.cmaj = fuse ? 1 : 0;
-  r.c.launch(r.c, r.s, r.pts, r.labels, at<float>(r.ws, L.cpar[r.cur]),
-             at<float4>(r.ws, L.shift[r.cur]), at<double>(r.ws, L.part), a);
+  const bool culled = r.cc.on && mode != kLabels;
+  const int nrows = culled ? r.cc.grid : r.c.grid;
+  if (culled) {
+    Cull4Args ca;
+    ca.n = r.n;
+    ca.ntiles = a.ntiles;
+    ca.K = r.K;
+    ca.mode = mode;
+    ca.ncols = L.ncols;
+    ca.scap = r.cc.scap;
+    ca.cmaj = a.cmaj;
+    hipLaunchKernelGGL(em4_cull_kernel<kCull4Waves>, dim3(r.cc.grid), dim3(kCull4Waves * 64),
+                       r.cc.lds, r.s, r.pts, at<float4>(r.ws, L.tsph),
+                       at<float>(r.ws, L.cpar[r.cur]), at<float4>(r.ws, L.shift[r.cur]),
+                       at<double>(r.ws, L.part), ca);
+  } else {
+    r.c.launch(r.c, r.s, r.pts, r.labels, at<float>(r.ws, L.cpar[r.cur]),
+               at<float4>(r.ws, L.shift[r.cur]), at<double>(r.ws, L.part), a);
+  }
   HIP_TRY(hipGetLastError());
   if (fuse) {
     const int nxt = 1 - r.cur;
     Fuse4Args fa;
     fa.K = r.K;
     fa.ncols = L.ncols;
-    fa.nrows = r.c.grid;
+    fa.nrows = nrows;
     fa.mode = mode;
     fa.umode = umode;
     fa.reg = reg;
@@ -216,7 +294,7 @@ gmm_status pass4(Run4 &r, int mode, int umode, double reg, double *slot,
     return GMM_OK;
   }
   hipLaunchKernelGGL(reduce4_kernel, dim3((L.ncols + 255) / 256, kRedChunks), dim3(256), 0,
-                     r.s, at<double>(r.ws, L.part), r.c.grid, L.ncols, at<double>(r.ws, L.red));
+                     r.s, at<double>(r.ws, L.part), nrows, L.ncols, at<double>(r.ws, L.red));
   HIP_TRY(hipGetLastError());
   const int nxt = 1 - r.cur;
   Upd4Args ua;
@@ -245,6 +323,51 @@ gmm_status check_fit4(int64_t n, int32_t k) {
 }
 
 
+// Culled fits: the points (and labels) in Morton order of their xyz part,
+// and the bounding sphere of every 64-point tile; r.pts / r.labels then
+// point at the ordered copies.  The sums of a pass are order-free, so only
+// the order of floating-point additions changes.
+gmm_status order4(Run4 &r) {
+  const Layout4 &L = r.L;
+  const int64_t n = r.n, npad = L.npad;
+  hipLaunchKernelGGL(bbox4_kernel, dim3(kBox4Blocks), dim3(kOrd), 0, r.s, r.pts, n,
+                     at<float>(r.ws, L.box6));
+  HIP_TRY(hipGetLastError());
+  const unsigned mb = (unsigned)std::min<int64_t>(256, (npad + kOrd - 1) / kOrd);
+  hipLaunchKernelGGL(morton4_kernel, dim3(mb), dim3(kOrd), 0, r.s, r.pts, n, npad,
+                     at<float>(r.ws, L.box6), kBox4Blocks, at<unsigned>(r.ws, L.keys[0]),
+                     at<unsigned>(r.ws, L.vals[0]));
+  HIP_TRY(hipGetLastError());
+  int src = 0;
+  for (int shift = 0; shift < 24; shift += 8, src = 1 - src) {
+    hipLaunchKernelGGL(gmm_dev::radix_hist_kernel, dim3(L.nblk), dim3(gmm_dev::kSortThreads), 0,
+                       r.s, at<unsigned>(r.ws, L.keys[src]), npad, shift,
+                       at<unsigned>(r.ws, L.hist), L.nblk);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(gmm_dev::radix_scan_kernel, dim3(256), dim3(gmm_dev::kSortThreads), 0,
+                       r.s, at<unsigned>(r.ws, L.hist), L.nblk, at<unsigned>(r.ws, L.dtot));
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(gmm_dev::radix_scatter_kernel, dim3(L.nblk), dim3(gmm_dev::kSortThreads),
+                       0, r.s, at<unsigned>(r.ws, L.keys[src]), at<unsigned>(r.ws, L.vals[src]),
+                       npad, shift, at<unsigned>(r.ws, L.hist), L.nblk,
+                       at<unsigned>(r.ws, L.dtot), at<unsigned>(r.ws, L.keys[1 - src]),
+                       at<unsigned>(r.ws, L.vals[1 - src]));
+    HIP_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(gather4_kernel, dim3((unsigned)((npad + kOrd - 1) / kOrd)), dim3(kOrd), 0,
+                     r.s, r.pts, r.labels, at<unsigned>(r.ws, L.vals[src]), n, npad,
+                     at<float4>(r.ws, L.spts), r.labels ? at<int32_t>(r.ws, L.slab) : nullptr);
+  HIP_TRY(hipGetLastError());
+  const int ntiles = (int)(npad / kT);
+  hipLaunchKernelGGL(tile_sphere4_kernel, dim3((unsigned)((ntiles + kOrd / 64 - 1) / (kOrd / 64))),
+                     dim3(kOrd), 0, r.s, at<float4>(r.ws, L.spts), n, ntiles,
+                     at<float4>(r.ws, L.tsph));
+  HIP_TRY(hipGetLastError());
+  r.pts = at<float4>(r.ws, L.spts);
+  if (r.labels) r.labels = at<int32_t>(r.ws, L.slab);
+  return GMM_OK;
+}
+
 // The whole fit on r.s: init, checks, theta_0, T iterations, the final
 // log-likelihood pass and the outputs.
 gmm_status enqueue4(Run4 &r, float *w, float *mu, float *cov, double *loglik,
@@ -259,6 +382,7 @@ gmm_status enqueue4(Run4 &r, float *w, float *mu, float *cov, double *loglik,
   hipLaunchKernelGGL(check4_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, r.s,
                      r.pts, r.labels, n, k, at<uint32_t>(ws, r.L.status));
   HIP_TRY(hipGetLastError());
+  if (r.cc.on && (st = order4(r)) != GMM_OK) return st;
   const double reg = opts->reg_covar;
   r.cur = 0;
   if (r.labels) {
@@ -301,12 +425,13 @@ struct Fit4Key {
   double reg;
   int k, iters, mode, dev;
   const void *tile;
-  bool fused;
+  bool fused, cull;
+  const void *ckfn;
   bool operator==(const Fit4Key &o) const {
     return pts == o.pts && labels == o.labels && w == o.w && mu == o.mu && cov == o.cov &&
            loglik == o.loglik && ws == o.ws && n == o.n && ws_bytes == o.ws_bytes &&
            reg == o.reg && k == o.k && iters == o.iters && mode == o.mode && dev == o.dev &&
-           tile == o.tile && fused == o.fused;
+           tile == o.tile && fused == o.fused && cull == o.cull && ckfn == o.ckfn;
   }
 };
 
@@ -372,7 +497,9 @@ size_t gmm4_fit_workspace_size(int64_t n, int32_t k, const gmm_fit_opts *opts) {
   if (check_fit4(n, k) != GMM_OK) return 0;
   Cfg4 c;
   if (!make_cfg4(k, n, &c)) return 0;
-  return layout4(k, c.grid).total;
+  CullCfg4 cc;
+  if (cull4_enabled() && !make_cull4(k, n, &cc)) return 0;
+  return layout4(k, std::max(c.grid, cc.grid), n, cc.on).total;
 }
 
 gmm_status gmm4_fit(const float *pts, int64_t n, int32_t k, const int32_t *init_labels,
@@ -396,7 +523,9 @@ gmm_status gmm4_fit(const float *pts, int64_t n, int32_t k, const int32_t *init_
   r.K = k;
   r.n = n;
   if (!make_cfg4(k, n, &r.c)) return fail(GMM_ERR_UNSUPPORTED, "no 4D launch configuration for k=%d", k);
-  r.L = layout4(k, r.c.grid);
+  if (cull4_enabled() && !make_cull4(k, n, &r.cc))
+    return fail(GMM_ERR_UNSUPPORTED, "no culled 4D launch configuration for k=%d", k);
+  r.L = layout4(k, std::max(r.c.grid, r.cc.grid), n, r.cc.on);
   r.s = static_cast<hipStream_t>(stream);
   WsGuard guard;
   if ((st = get_ws(&ws, &ws_bytes, r.L.total, r.s, &guard)) != GMM_OK) return st;
@@ -413,7 +542,7 @@ gmm_status gmm4_fit(const float *pts, int64_t n, int32_t k, const int32_t *init_
   // first runs directly, the second captures); not with a temporary workspace
   if (graphs_enabled() && !guard.ptr) {
     Fit4Key key{pts, init_labels, w, mu, cov, loglik, ws, n, ws_bytes, opts->reg_covar,
-                k, opts->iters, opts->moment_mode, 0, r.c.kfn, r.fused};
+                k, opts->iters, opts->moment_mode, 0, r.c.kfn, r.fused, r.cc.on, r.cc.kfn};
     (void)hipGetDevice(&key.dev);
     std::lock_guard<std::mutex> lk(g_graph4_mu);
     bool found = false;

@@ -306,3 +306,57 @@ def test_graph_replay_is_bitwise_equal_to_direct_launches():
             np.testing.assert_array_equal(a, b)
     Lr = o4.fit(X.astype(np.float64), K, 1e-3, T, labels=lab)[3]
     assert np.abs(outs[0][3] - Lr).max() <= 1e-4 * max(np.abs(Lr).max(), X.shape[0])
+
+
+# ------------------------------------------------------------ culled passes
+
+def _blob4(n, seed):
+    """One anisotropic 4D blob: every component of a fit overlaps every tile."""
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=(4, 4)) * 0.3
+    return (rng.normal(size=(n, 4)) @ A + np.array([2.0, -1.0, 4.0, 0.5])).astype(np.float32)
+
+
+@pytest.mark.parametrize("what,K,n", [("frame", 7, 5003), ("frame", 100, 40000),
+                                      ("frame", 300, 30011), ("blob", 300, 20000)])
+def test_culled_passes_equal_dense_passes(what, K, n, monkeypatch):
+    """The default culled soft passes (points in Morton order, pairs with a
+    zero FP32 weight on the whole tile skipped) against the dense kernel
+    (GMM_CULL4=0) on the same fit: L at every iteration within 1e-6 (floor
+    N) and the parameters within 1e-5, i.e. equal up to the order of FP32
+    additions.  The blob makes every tile see every component, so a tile's
+    active components exceed the 128 E rows and the later rows are
+    recomputed."""
+    _case("4D culled vs dense %s K=%d n=%d" % (what, K, n))
+    X = _frame4(n, seed=K + 5) if what == "frame" else _blob4(n, K)
+    lab = _labels(X, K, 4)
+    T = 5
+    wc, muc, covc, Lc = _gpu_fit(X, K, T, labels=lab)
+    monkeypatch.setenv("GMM_CULL4", "0")
+    wd, mud, covd, Ld = _gpu_fit(X, K, T, labels=lab)
+    eL = float(np.max(np.abs(Lc - Ld) / np.maximum(np.abs(Ld), n)))
+    e = mixture_errors((wc, muc, covc), (wd, mud, covd), X)
+    print("L", eL, e, flush=True)
+    assert eL <= 1e-6, eL
+    assert max(e.values()) <= 1e-5, e
+
+
+def test_culled_one_step_with_far_points():
+    """One E+M step from fitted parameters on a cloud with 37 points 60 m
+    away from every component: those points take the far-point path (their
+    own maximum over all K components) in the culled pass; against the
+    oracle's step at the one-step bar."""
+    _case("4D culled far points")
+    X0 = _frame4(20000, seed=12)
+    K = 50
+    lab = _labels(X0, K, 2)
+    theta = _theta32(o4.fit(X0, K, 1e-3, 2, labels=lab)[:3])
+    far = (np.random.default_rng(5).normal(size=(37, 4)) * 0.5 +
+           np.array([60.0, 60.0, 60.0, 0.5])).astype(np.float32)
+    X = np.concatenate([X0[:9000], far, X0[9000:]])
+    w, mu, cov, L = _gpu_fit(X, K, 1, theta0=theta)
+    wr, mur, covr, L0 = o4.em_step(X.astype(np.float64), *theta, 1e-3)
+    e = mixture_errors((w, mu, cov), (wr, mur, covr), X)
+    e["L0"] = abs(L[0] - L0) / max(abs(L0), X.shape[0])
+    print(e, flush=True)
+    assert max(e.values()) <= 1e-5, e
