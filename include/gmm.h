@@ -258,10 +258,12 @@ const char *gmm_fit_batched_config(int32_t B, const int64_t *pt_off, const int32
  *   labels[i] = the nearest centre, the lowest j on ties.
  * Distances are ((dx^2 + dy^2) + dz^2) in double, each operation rounded
  * on its own.  The running sums have a fixed order - sequential within
- * chunks of 256 points, chunk totals sequential within groups of 64
- * chunks, group totals sequential; the search walks groups, then chunks,
- * then points - so the centres are reproducible and equal those of any
- * implementation that follows the same order.
+ * chunks of 256 points, chunk totals sequential in runs of 16 from offsets
+ * formed by a fixed block scan, inside the chosen chunk a fixed block scan
+ * from its running sum; the pick is the first positive entry above u_j W
+ * (else the last positive entry) - so the centres are reproducible; where
+ * u_j W lies within rounding of a running sum another correct order may
+ * pick a neighbouring point.
  *
  * pts: device, n x 3 float32.  u: device, k doubles.  centres: device, k
  * int64 indices into pts (output).  labels: device, n int32 in [0, k)

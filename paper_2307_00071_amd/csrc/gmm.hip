@@ -2038,19 +2038,17 @@ gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
 // ------------------------------------------------------- k-means++ seeding
 
 struct KppLayout {
-  size_t status, D, T, U, total;
-  int64_t nch, ngr;
+  size_t status, D, T, total;
+  int64_t nch;
 };
 
 KppLayout kpp_layout(int64_t n) {
   KppLayout L;
   L.nch = (n + kKppChunk - 1) / kKppChunk;
-  L.ngr = (L.nch + kKppGroup - 1) / kKppGroup;
   size_t o = 0;
   L.status = o; o = align256(o + sizeof(uint32_t));
   L.D = o; o = align256(o + (size_t)n * sizeof(double));
   L.T = o; o = align256(o + (size_t)L.nch * sizeof(double));
-  L.U = o; o = align256(o + (size_t)L.ngr * sizeof(double));
   L.total = o;
   return L;
 }
@@ -2073,7 +2071,7 @@ gmm_status gmm_kmeanspp(const float *pts, int64_t n, int32_t k, const double *u,
   WsGuard guard;
   if ((st = get_ws(&ws, &ws_bytes, L.total, s, &guard)) != GMM_OK) return st;
   uint32_t *status = at<uint32_t>(ws, L.status);
-  double *D = at<double>(ws, L.D), *T = at<double>(ws, L.T), *U = at<double>(ws, L.U);
+  double *D = at<double>(ws, L.D), *T = at<double>(ws, L.T);
   hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, s, status, nullptr, 0,
                      nullptr, 0);
   HIP_TRY(hipGetLastError());
@@ -2086,8 +2084,8 @@ gmm_status gmm_kmeanspp(const float *pts, int64_t n, int32_t k, const double *u,
                        dim3(kKppUpdThreads), 0, s, pts, n, centres, j - 1, D, T, L.nch,
                        status);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(kpp_select_kernel, dim3(1), dim3(kKppSelThreads), 0, s, D, T, U,
-                       n, u, j, centres);
+    hipLaunchKernelGGL(kpp_select_kernel, dim3(1), dim3(kKppSelThreads), 0, s, D, T, n, u, j,
+                       centres);
     HIP_TRY(hipGetLastError());
   }
   if (!labels && k == 1) {  // no distances formed: check the points alone

@@ -11,16 +11,14 @@
 //     W = 0 centre j repeats centre j - 1;
 //   label_i = the nearest centre, the lowest index on ties.
 // The running sums have a fixed order so that the choice is reproducible:
-// sequential within chunks of kKppChunk points, chunk totals sequential
-// within groups of kKppGroup chunks, group totals sequential.  The search
-// walks the groups, then the chunks of the chosen group, then the points of
-// the chosen chunk, each time against what is left of u W; where rounding
-// leaves no running sum above it, the last positive entry is taken.
+// sequential within chunks of kKppChunk points, chunk totals sequential in
+// runs of 16 from offsets formed by a block scan (kpp_select_kernel); the
+// pick is the first positive entry above u W, else the last positive entry.
 // Squared distances are ((dx^2 + dy^2) + dz^2) in double with every
 // operation rounded on its own (no contraction).
 //
 // Per round j >= 1: kpp_update_kernel (D2 with centre j - 1, chunk totals)
-// and kpp_select_kernel (one block: group totals, W, the search).  The
+// and kpp_select_kernel (one block: W, the chunk, the point).  The
 // update streams 28 B per point per round (the point, D2 read and
 // written); the select kernel is a short chain of dependent reads and
 // serial sums; neither does enough arithmetic to meet a compute roofline.
@@ -32,7 +30,6 @@
 namespace gmm_dev {
 
 constexpr int kKppChunk = 256;      // points per chunk (running-sum order)
-constexpr int kKppGroup = 64;       // chunks per group
 constexpr int kKppSelThreads = 1024;
 constexpr int kKppLabelThreads = 256;
 
@@ -108,214 +105,163 @@ __global__ __launch_bounds__(kKppUpdThreads) void kpp_update_kernel(
   }
 }
 
-// Sequential total of the chunk totals of group g (16 loads in flight).
-__device__ __forceinline__ double kpp_group_total(const double *__restrict__ T, int64_t nch,
-                                                  int64_t g) {
-  const int64_t lo = g * kKppGroup;
-  const int cnt = (int)(nch - lo < kKppGroup ? nch - lo : kKppGroup);
-  double s = 0.0;
-  int c = 0;
-  for (; c + 16 <= cnt; c += 16) {
-    double v[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = T[lo + c + q];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) s += v[q];
-  }
-  for (; c < cnt; ++c) s += T[lo + c];
-  return s;
-}
+// ---- centre j >= 1: one block of kKppSelThreads threads.
+// The running sums in index order are formed as: chunk totals (sequential
+// over 256 points, kpp_update_kernel); kKppSelPer consecutive chunk totals
+// per thread of a stage of kKppSelThreads x kKppSelPer chunks, sequential
+// from the thread's offset; the thread offsets by a block scan of the
+// thread sums (a shuffle scan in each wave, the wave totals in order); the
+// stages in order.  Inside the chosen chunk the 256 D2 by the same block
+// scan from the chunk's running sum.  The pick is the first positive entry
+// whose running sum exceeds t = u_j W (the exact running sum is flat over
+// zero entries, so none of them is ever the first above a level); where
+// rounding leaves no entry above t, the last positive entry.
+constexpr int kKppSelPer = 16;
+constexpr int64_t kKppSelStage = (int64_t)kKppSelThreads * kKppSelPer;
 
-// Result of one walk over an array.
-struct KppWalk {
-  double total;        // running sum at the end
-  double before;       // running sum before `idx`
-  long long idx;       // first index whose running sum exceeds t, else the
-                       // last positive entry, else -1
-  long long hit, last; // block reductions (LDS)
-};
-
-// out->hit = min index of the block's threads with `above`, out->last = max
-// index with `positive`: per wave a ballot, then one LDS atomic per wave.
-__device__ __forceinline__ void kpp_mark(bool above, bool positive, KppWalk *out) {
-  const uint64_t a = __ballot(above), p = __ballot(positive);
-  if ((threadIdx.x & 63) == 0) {
-    const int wbase = threadIdx.x & ~63;
-    if (a) atomicMin(reinterpret_cast<unsigned long long *>(&out->hit),
-                     (unsigned long long)(wbase + __builtin_ctzll(a)));
-    if (p) atomicMax(&out->last, (long long)(wbase + 63 - __builtin_clzll(p)));
+// Exclusive prefix of v over the block and the block total (*tot).  wtot:
+// kKppSelThreads / 64 + 1 doubles of LDS.  Three barriers.
+__device__ __forceinline__ double kpp_block_scan(double v, double *wtot, double *tot) {
+  constexpr int NWV = kKppSelThreads / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double s = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const double o = __shfl_up(s, off, 64);
+    if (lane >= off) s += o;
   }
-}
-
-// v[0..m) in order.  Per stage of kKppSelThreads entries thread 0 forms the
-// running sums sequentially (only the dependent additions are serial; the
-// values are read 16 at a time) into `pre`; then every thread compares
-// its own entry with t, and the first index above t (or the last positive
-// entry) is found by block-wide minimum / maximum.  Same values and the
-// same choice as a single sequential walk.
-__device__ void kpp_walk(const double *__restrict__ v, int64_t m, bool search, double t,
-                         double *stage, double *pre, KppWalk *out) {
-  double acc = 0.0;  // thread 0: running sum before this stage
-  bool found = false;
-  for (int64_t base = 0; base < m; base += kKppSelThreads) {
-    const int cnt = (int)(m - base < kKppSelThreads ? m - base : kKppSelThreads);
-    __syncthreads();  // stage and pre free; out->hit / out->last reset
-    if (threadIdx.x == 0) {
-      out->hit = -1;
-      out->last = -1;
-    }
-    // zeros past the end leave the running sums unchanged and are never
-    // above t or positive, so the walk needs no bounds inside
-    stage[threadIdx.x] = threadIdx.x < cnt ? v[base + threadIdx.x] : 0.0;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double a = acc;
-      for (int k0 = 0; k0 < cnt; k0 += 16) {
-        double e[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) e[q] = stage[k0 + q];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          a = a + e[q];
-          pre[k0 + q] = a;
-        }
-      }
-      pre[kKppSelThreads] = acc;  // running sum before the stage
-      acc = a;
-    }
-    __syncthreads();
-    kpp_mark(threadIdx.x < cnt && search && pre[threadIdx.x] > t,
-             threadIdx.x < cnt && stage[threadIdx.x] > 0.0, out);
-    __syncthreads();
-    // hit: -1 is the largest unsigned value, so atomicMin keeps any real index
-    if (out->hit >= 0 && out->hit < cnt) {
-      if (threadIdx.x == 0) {
-        const int h = (int)out->hit;
-        out->idx = base + h;
-        out->before = h > 0 ? pre[h - 1] : pre[kKppSelThreads];
-        out->total = acc;
-      }
-      found = true;
-      break;
-    }
-    if (threadIdx.x == 0 && out->last >= 0) {
-      const int l = (int)out->last;
-      out->idx = base + l;  // last positive so far
-      out->before = l > 0 ? pre[l - 1] : pre[kKppSelThreads];
-    }
-  }
-  if (!found && threadIdx.x == 0) out->total = acc;
-  __syncthreads();
-}
-
-// W and the group search in one pass when the group totals fit one stage:
-// the running sums of stage[0..m) (m <= kKppSelThreads) serially into pre,
-// W = the last, t = uj W, then the first running sum above t (else the
-// last positive entry) in parallel.  out->idx = -2 when W is not positive.
-__device__ void kpp_draw_walk(int m, double uj, double *stage, double *pre, KppWalk *out) {
-  // stage[0..kKppSelThreads) holds v, zeros past m (see kpp_walk)
-  if (threadIdx.x == 0) {
-    out->hit = -1;
-    out->last = -1;
-  }
+  double e = __shfl_up(s, 1, 64);
+  if (lane == 0) e = 0.0;
+  __syncthreads();   // wtot free
+  if (lane == 63) wtot[w] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double a = 0.0;
-    for (int k0 = 0; k0 < m; k0 += 16) {
-      double e[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) e[q] = stage[k0 + q];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        a = a + e[q];
-        pre[k0 + q] = a;
-      }
+    double acc = 0.0;
+    for (int k = 0; k < NWV; ++k) {
+      const double t = wtot[k];
+      wtot[k] = acc;
+      acc += t;
     }
-    out->total = a;
+    wtot[NWV] = acc;
   }
   __syncthreads();
-  const double W = out->total;
+  *tot = wtot[NWV];
+  return wtot[w] + e;
+}
+
+// hit = min of the indices `a` >= 0, lastp = max of the indices `l` >= 0
+// over the block; indices grow with the lane, so per wave the first (last)
+// flagged lane holds the wave's minimum (maximum): one LDS atomic per wave.
+__device__ __forceinline__ void kpp_wave_mark(long long a, long long l,
+                                              unsigned long long *hit, long long *lastp) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t ab = __ballot(a >= 0), lb = __ballot(l >= 0);
+  if (ab && lane == __builtin_ctzll(ab)) atomicMin(hit, (unsigned long long)a);
+  if (lb && lane == 63 - __builtin_clzll(lb)) atomicMax(lastp, l);
+}
+
+__global__ __launch_bounds__(kKppSelThreads) void kpp_select_kernel(
+    const double *__restrict__ D, const double *__restrict__ T, int64_t n,
+    const double *__restrict__ u, int j, int64_t *__restrict__ cidx) {
+  __shared__ double wtot[kKppSelThreads / 64 + 1];
+  __shared__ unsigned long long hit;   // smallest index above t (~0: none)
+  __shared__ long long lastp;          // largest positive index (-1: none)
+  __shared__ double hbefore, lbefore;  // running sum before the hit / last
+  const int tid = threadIdx.x;
+  const int64_t nch = (n + kKppChunk - 1) / kKppChunk;
+  const int64_t nst = (nch + kKppSelStage - 1) / kKppSelStage;
+  double uj = u[j];
+  if (!(uj >= 0.0 && uj < 1.0)) uj = 0.0;  // reported by kpp_first_kernel
+  double v[kKppSelPer];
+  double off = 0.0, stot = 0.0;
+  auto stage = [&](int64_t st) {   // v, this thread's offset in the stage, the stage total
+    const int64_t c0 = st * kKppSelStage + (int64_t)tid * kKppSelPer;
+#pragma unroll
+    for (int q = 0; q < kKppSelPer; ++q) v[q] = (c0 + q < nch) ? T[c0 + q] : 0.0;
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < kKppSelPer; ++q) sum += v[q];
+    off = kpp_block_scan(sum, wtot, &stot);
+  };
+  // W: the stage totals in order
+  double W = 0.0;
+  for (int64_t st = 0; st < nst; ++st) {
+    stage(st);
+    W += stot;
+  }
   if (!(W > 0.0)) {
-    if (threadIdx.x == 0) out->idx = -2;
-    __syncthreads();
+    if (tid == 0) cidx[j] = cidx[j - 1];
     return;
   }
   const double t = uj * W;
-  kpp_mark(threadIdx.x < m && pre[threadIdx.x] > t, threadIdx.x < m && stage[threadIdx.x] > 0.0,
-           out);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const long long h = out->hit >= 0 ? out->hit : out->last;
-    out->idx = h;
-    out->before = h > 0 ? pre[h - 1] : 0.0;
-  }
-  __syncthreads();
-}
-
-// Centre j >= 1 from the chunk totals T (group totals formed here; U is
-// scratch for more than kKppSelThreads groups) and the per-point D2.  One
-// block.
-__global__ __launch_bounds__(kKppSelThreads) void kpp_select_kernel(
-    const double *__restrict__ D, const double *__restrict__ T, double *__restrict__ U,
-    int64_t n, const double *__restrict__ u, int j, int64_t *__restrict__ cidx) {
-  __shared__ double stage[kKppSelThreads];
-  __shared__ double pre[kKppSelThreads + 1];
-  __shared__ KppWalk w;
-  const int64_t nch = (n + kKppChunk - 1) / kKppChunk;
-  const int64_t ngr = (nch + kKppGroup - 1) / kKppGroup;
-  double uj = u[j];
-  if (!(uj >= 0.0 && uj < 1.0)) uj = 0.0;  // reported by kpp_first_kernel
-  double t;
-  if (ngr <= kKppSelThreads) {
-    stage[threadIdx.x] = threadIdx.x < ngr ? kpp_group_total(T, nch, threadIdx.x) : 0.0;
-    kpp_draw_walk((int)ngr, uj, stage, pre, &w);
-    if (w.idx == -2) {
-      if (threadIdx.x == 0) cidx[j] = cidx[j - 1];
-      return;
+  // the chunk: first positive chunk total whose running sum exceeds t
+  int64_t c = -1, cl = -1;
+  double cbefore = 0.0, clbefore = 0.0, base = 0.0;
+  for (int64_t st = 0; st < nst; ++st) {
+    if (nst > 1) stage(st);
+    __syncthreads();
+    if (tid == 0) {
+      hit = ~0ull;
+      lastp = -1;
     }
-    t = uj * w.total;
-  } else {
-    for (int64_t g = threadIdx.x; g < ngr; g += kKppSelThreads) U[g] = kpp_group_total(T, nch, g);
-    if (threadIdx.x == 0) w.idx = -1;
     __syncthreads();
-    kpp_walk(U, ngr, false, 0.0, stage, pre, &w);
-    const double W = w.total;
-    if (!(W > 0.0)) {
-      if (threadIdx.x == 0) cidx[j] = cidx[j - 1];
-      return;
+    double acc = base + off;
+    long long mine = -1, myl = -1;
+    double mb = 0.0, mlb = 0.0;
+#pragma unroll
+    for (int q = 0; q < kKppSelPer; ++q) {
+      const double nxt = acc + v[q];
+      if (v[q] > 0.0) {
+        if (mine < 0 && nxt > t) {
+          mine = (long long)tid * kKppSelPer + q;
+          mb = acc;
+        }
+        myl = (long long)tid * kKppSelPer + q;
+        mlb = acc;
+      }
+      acc = nxt;
     }
-    t = uj * W;
+    kpp_wave_mark(mine, myl, &hit, &lastp);
     __syncthreads();
-    if (threadIdx.x == 0) w.idx = -1;
+    if (mine >= 0 && (unsigned long long)mine == hit) hbefore = mb;
+    if (myl >= 0 && myl == lastp) lbefore = mlb;
     __syncthreads();
-    kpp_walk(U, ngr, true, t, stage, pre, &w);
+    if (hit != ~0ull) {
+      c = st * kKppSelStage + (int64_t)hit;
+      cbefore = hbefore;
+      break;
+    }
+    if (lastp >= 0) {
+      cl = st * kKppSelStage + lastp;
+      clbefore = lbefore;
+    }
+    base += stot;
   }
-  // (an index < 0 cannot follow W > 0; kept as a guard for the indexing)
-  if (w.idx < 0) {
-    if (threadIdx.x == 0) cidx[j] = cidx[j - 1];
+  if (c < 0) {
+    c = cl;
+    cbefore = clbefore;
+  }
+  if (c < 0) {  // a guard: W > 0 has a positive chunk
+    if (tid == 0) cidx[j] = cidx[j - 1];
     return;
   }
-  const int64_t g = w.idx;
-  const double t1 = t - w.before;
-  const int64_t clo = g * kKppGroup;
-  const int64_t cm = nch - clo < kKppGroup ? nch - clo : kKppGroup;
+  // the point: first positive D2 of chunk c whose running sum exceeds t
+  const int64_t i0 = c * kKppChunk;
+  const double x = (tid < kKppChunk && i0 + tid < n) ? D[i0 + tid] : 0.0;
+  double ctot = 0.0;
+  const double pre = cbefore + kpp_block_scan(x, wtot, &ctot);
   __syncthreads();
-  if (threadIdx.x == 0) w.idx = -1;
-  __syncthreads();
-  kpp_walk(T + clo, cm, true, t1, stage, pre, &w);
-  if (w.idx < 0) {
-    if (threadIdx.x == 0) cidx[j] = cidx[j - 1];
-    return;
+  if (tid == 0) {
+    hit = ~0ull;
+    lastp = -1;
   }
-  const int64_t c = clo + w.idx;
-  const double t2 = t1 - w.before;
-  const int64_t ilo = c * kKppChunk;
-  const int64_t im = n - ilo < kKppChunk ? n - ilo : kKppChunk;
   __syncthreads();
-  if (threadIdx.x == 0) w.idx = -1;
+  kpp_wave_mark((x > 0.0 && pre + x > t) ? (long long)tid : -1, x > 0.0 ? (long long)tid : -1,
+                &hit, &lastp);
   __syncthreads();
-  kpp_walk(D + ilo, im, true, t2, stage, pre, &w);
-  if (threadIdx.x == 0) cidx[j] = w.idx < 0 ? cidx[j - 1] : ilo + w.idx;
+  if (tid == 0) {
+    const long long p = hit != ~0ull ? (long long)hit : lastp;
+    cidx[j] = p >= 0 ? i0 + p : cidx[j - 1];
+  }
 }
 
 // Non-finite coordinates (for a call that forms no distances otherwise).

@@ -67,9 +67,12 @@ def check_trajectory(X, u, centres, sum_terms):
 
 
 def gpu_sum_terms(N):
-    """Rounding budget of running sums built from chunks of 256 points,
-    chunk totals in groups of 64 and sequential group totals: at most
-    256 + 64 + ceil(N / 16384) additions along a running sum, as many for
-    the total W."""
-    groups = -(-N // (256 * 64))
-    return 2 * (256 + 64 + groups)
+    """Rounding budget of the GPU's running sums: chunks of 256 points
+    (sequential), 16 chunk totals per thread (sequential) from an offset
+    formed by a block scan of 1024 thread sums (6 shuffle levels, then 16
+    wave totals in order), stages of 16,384 chunks in order, and inside the
+    chosen chunk a block scan of its 256 terms (8 levels) from the chunk's
+    running sum: at most 256 + 16 + 6 + 16 + 8 + ceil(N / 2^22) additions
+    along a running sum, as many for the total W."""
+    stages = -(-N // (256 * 16384))
+    return 2 * (256 + 16 + 6 + 16 + 8 + stages)

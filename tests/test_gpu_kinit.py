@@ -2,7 +2,8 @@
 definition and the oracle.
 
 The GPU turns a draw into an index through chunked running sums (256
-points, 64-chunk groups, group totals); the oracle through one flat running
+points per chunk, chunk totals in runs of 16 from block-scan offsets, a
+block scan inside the chosen chunk); the oracle through one flat running
 sum.  Floating-point running sums depend on their order, so the two may
 part only where u_j W lies within rounding of a running sum.  Every GPU
 seeding is therefore checked along its own trajectory against the exact
@@ -99,7 +100,7 @@ def test_kmeanspp_lidar_scan_full():
 
 
 def test_kmeanspp_more_groups_than_one_stage():
-    """n > 1024 groups of 64 x 256 points: the group totals are walked in
+    """n > 16,384 chunks of 256 points: the chunk totals are scanned in
     stages (the staged search path)."""
     _case("kmeanspp n=17000000 K=4")
     X = np.random.default_rng(8).uniform(-50, 50, (17_000_000, 3)).astype(np.float32)
