@@ -209,12 +209,28 @@ gmm_status run_meanshift(const MsLayout &L, void *ws, hipStream_t s, const float
   HIP_TRY(hipGetLastError());
   if ((st = build_grid(L, ws, s, n, &cnt->ncells)) != GMM_OK) return st;
 
-  // ---- every seed to its mode (one wave each; at most n seeds)
+  // ---- every seed to its mode (at most n seeds; the count is on the
+  // device): one wave per seed, or a block per seed when there are at most
+  // thr seeds; each kernel returns at once when the other one applies.
+  // GMM_MS_SEED_WAVES=1|4 forces one form (tests of both on one input).
+  int thr = kMsBlockSeeds;
+  if (const char *e = getenv("GMM_MS_SEED_WAVES")) {
+    if (e[0] == '1') thr = 0;
+    if (e[0] == '4') thr = (int)std::min<int64_t>(n, INT32_MAX);
+  }
   hipLaunchKernelGGL(ms_shift_kernel<D>, dim3(blocks(n, kMsWaves)), dim3(kMsThreads), 0, s,
                      at<float4>(ws, L.ptsS), at<int>(ws, L.start), at<uint64_t>(ws, L.ckey),
                      &cnt->ncells, at<uint64_t>(ws, L.hk), at<int>(ws, L.hv), L.cap - 1, h,
-                     max_iter, mode, weight, iters, &cnt->max_it);
+                     max_iter, mode, weight, iters, &cnt->max_it, thr);
   HIP_TRY(hipGetLastError());
+  if (thr > 0) {
+    hipLaunchKernelGGL(ms_shift4_kernel<D>, dim3((unsigned)std::min<int64_t>(n, thr)),
+                       dim3(kMsThreads), 0, s, at<float4>(ws, L.ptsS), at<int>(ws, L.start),
+                       at<uint64_t>(ws, L.ckey), &cnt->ncells, at<uint64_t>(ws, L.hk),
+                       at<int>(ws, L.hv), L.cap - 1, h, max_iter, mode, weight, iters,
+                       &cnt->max_it, thr);
+    HIP_TRY(hipGetLastError());
+  }
 
   // ---- the mode grid over the same buffers; perm2 (sorted -> seed) in vA
   hipLaunchKernelGGL(ms_mode_key_kernel<D>, dim3(blocks(n, kSortThreads)), dim3(kSortThreads),

@@ -353,6 +353,7 @@ struct GridQuery {
 // therefore sums its points in an order fixed by the cells alone: the mean
 // of an iterate depends only on the set of points within h of it.
 constexpr int kMsSerial = 16;
+constexpr int kMsBlockSeeds = 16384;   // at most this many seeds: four waves per seed
 
 template <int D>
 __device__ __forceinline__ void ms_take(const float4 &x, bool ok, const double *s, double h2,
@@ -377,10 +378,12 @@ __global__ __launch_bounds__(kMsThreads) void ms_shift_kernel(
     const uint64_t *__restrict__ ckey, const int *__restrict__ ncp,
     const uint64_t *__restrict__ hk, const int *__restrict__ hv, uint64_t mask,
     double h, int max_iter, double *__restrict__ mode, int *__restrict__ weight,
-    int *__restrict__ iters, int *__restrict__ max_it) {
+    int *__restrict__ iters, int *__restrict__ max_it, int thr) {
   const int lane = threadIdx.x & 63;
   const int c = blockIdx.x * kMsWaves + (threadIdx.x >> 6);
-  if (c >= *ncp) return;   // uniform per wave
+  const int ncells = *ncp;
+  if (ncells <= thr) return;   // few seeds: ms_shift4_kernel takes them
+  if (c >= ncells) return;     // uniform per wave
   double s[D];
   {
     int64_t b[D];
@@ -451,6 +454,134 @@ __global__ __launch_bounds__(kMsThreads) void ms_shift_kernel(
     ++it;
   }
   if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) mode[(size_t)c * D + j] = s[j];
+    weight[c] = cnt;
+    iters[c] = it;
+    atomicMax(max_it, it);
+  }
+}
+
+// The same shift with the four waves of a block on one seed, for calls with
+// at most `thr` seeds (few seeds, large neighbourhoods: the time is the
+// slowest seed's chain of iterations).  Wave w probes the slots of rounds
+// w, w + 4, ... and walks their small cells lane by lane; the wide cells of
+// every round go to LDS in slot order and all 256 lanes walk them one
+// after another (point b + k to thread k mod 256); the four wave sums are
+// added in wave order.  Every lane's order is again fixed by the cells
+// alone.  Two barriers per iteration.
+template <int D>
+__global__ __launch_bounds__(kMsThreads) void ms_shift4_kernel(
+    const float4 *__restrict__ ptsS, const int *__restrict__ cstart,
+    const uint64_t *__restrict__ ckey, const int *__restrict__ ncp,
+    const uint64_t *__restrict__ hk, const int *__restrict__ hv, uint64_t mask,
+    double h, int max_iter, double *__restrict__ mode, int *__restrict__ weight,
+    int *__restrict__ iters, int *__restrict__ max_it, int thr) {
+  constexpr int NR = (1 << (2 * D)) / 64;   // rounds of 64 slots
+  constexpr int NW = kMsThreads / 64;
+  __shared__ int wb[NR][64], we[NR][64];    // wide cells of each round, slot order
+  __shared__ int wn[NR];
+  __shared__ double part[NW][D + 1];
+  const int ncells = *ncp;
+  if (ncells > thr) return;                 // many seeds: ms_shift_kernel takes them
+  const int c = blockIdx.x;
+  if (c >= ncells) return;                  // uniform per block
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double s[D];
+  {
+    int64_t b[D];
+    unpack_key<D>(ckey[c], b);
+#pragma unroll
+    for (int j = 0; j < D; ++j) s[j] = (double)b[j] * h;
+  }
+  const double h2 = h * h;
+  const double stop = 1e-3 * h;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int it = 0, cnt = 0;
+  for (;;) {
+    GridQuery<D> g;
+    g.init(s, h);
+    double acc[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) acc[j] = 0.0;
+    int in = 0;
+    for (int r = w; r < NR; r += NW) {
+      int b = 0, e = 0;
+      uint64_t key;
+      if (g.slot_key(r * 64 + lane, &key)) {
+        const int id = hash_find(hk, hv, mask, key);
+        if (id >= 0) {
+          b = cstart[id];
+          e = cstart[id + 1];
+        }
+      }
+      const bool wide = e - b > kMsSerial;
+      if (!wide) {
+        for (int p0 = b; p0 < e; p0 += 4) {
+          float4 x[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) x[k] = ptsS[min(p0 + k, e - 1)];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) ms_take<D>(x[k], p0 + k < e, s, h2, acc, in);
+        }
+      }
+      const uint64_t bm = __ballot(wide);
+      if (wide) {
+        const int pos = __popcll(bm & below);
+        wb[r][pos] = b;
+        we[r][pos] = e;
+      }
+      if (lane == 0) wn[r] = __popcll(bm);
+    }
+    __syncthreads();                                                  // 1
+    for (int r = 0; r < NR; ++r) {
+      const int nw = wn[r];
+      for (int k = 0; k < nw; ++k) {
+        const int bw = wb[r][k], ew = we[r][k];
+        for (int p0 = bw + (int)threadIdx.x; p0 < ew; p0 += 4 * kMsThreads) {
+          float4 x[4];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) x[kk] = ptsS[min(p0 + kMsThreads * kk, ew - 1)];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+            ms_take<D>(x[kk], p0 + kMsThreads * kk < ew, s, h2, acc, in);
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) acc[j] = acc[j] + __shfl_xor(acc[j], off, 64);
+      in += __shfl_xor(in, off, 64);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) part[w][j] = acc[j];
+      part[w][D] = (double)in;
+    }
+    __syncthreads();                                                  // 2
+    double tot[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) tot[j] = part[0][j];
+    int tin = (int)part[0][D];
+#pragma unroll
+    for (int v = 1; v < NW; ++v) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) tot[j] = tot[j] + part[v][j];
+      tin += (int)part[v][D];
+    }
+    if (tin == 0) break;   // uniform: every thread read the same sums
+    cnt = tin;
+    double d[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const double v = tot[j] / (double)tin;
+      d[j] = v - s[j];
+      s[j] = v;
+    }
+    if (sqrt(sq_norm<D>(d)) <= stop || it == max_iter) break;
+    ++it;
+  }
+  if (threadIdx.x == 0) {
 #pragma unroll
     for (int j = 0; j < D; ++j) mode[(size_t)c * D + j] = s[j];
     weight[c] = cnt;

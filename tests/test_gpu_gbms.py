@@ -19,6 +19,8 @@ What is compared:
     the merge by the two properties that make a kept set the greedy one
     (no two kept modes within h; every removed mode has a kept predecessor
     within h);
+  * both forms of the shift (one wave per seed, four waves per seed) on one
+    input with wide cells;
   * determinism (two calls bitwise equal), the error paths and the
     degenerate clouds (one point, identical points, points on bin edges,
     n = 0, max_iter = 0).
@@ -177,6 +179,35 @@ def test_full_frame_sampled(h):
     np.testing.assert_array_equal(w, info["seed_weights"][kept])
     print("seeds", S, "K", info["n_modes"], "rounds", info["rounds"],
           "max iters", info["max_iters"], flush=True)
+
+
+def test_one_and_four_waves_per_seed(monkeypatch):
+    """Both forms of the shift (one wave per seed; a block of four waves per
+    seed, the default at most 16,384 seeds) on the 320 x 240 frame at h = 0.2:
+    2,324 seeds whose neighbourhoods hold wide cells.  Each form against the
+    oracle on sampled seeds (the slowest included), its merge exact, and the
+    two forms' kept sets and weights equal, their modes within the per-seed
+    bar of each other."""
+    _case("one and four waves per seed h=0.2")
+    X = _frame_320x240()
+    h = 0.2
+    out = {}
+    for waves in ("1", "4"):
+        monkeypatch.setenv("GMM_MS_SEED_WAVES", waves)
+        modes, w, info = _run(X, h)
+        S = info["n_seeds"]
+        rng = np.random.default_rng(21)
+        idx = np.unique(np.concatenate([[0, S - 1, int(np.argmax(info["seed_iters"]))],
+                                        rng.choice(S, 16, replace=False)]))
+        _check_seeds(X, h, info, idx)
+        _check_merge_exact(h, info)
+        out[waves] = (modes, w, info)
+        print(waves, "wave(s): seeds", S, "K", info["n_modes"], "max iters",
+              info["max_iters"], flush=True)
+    (m1, w1, i1), (m4, w4, i4) = out["1"], out["4"]
+    np.testing.assert_array_equal(i1["seed_status"], i4["seed_status"])
+    np.testing.assert_array_equal(w1, w4)
+    assert np.abs(m1 - m4).max() <= 2 * _tol(X, h)
 
 
 def test_bitwise_deterministic():
