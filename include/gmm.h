@@ -385,13 +385,17 @@ const char *gmm_tile_config(int64_t n, int32_t k);
  *               1 kept / 2 removed by the merge / 3 dropped.
  *  info         host: seeds, K, merge rounds, largest iteration count.
  *  Synchronises: the merge checks its progress on the host every 16 rounds
- *  and the call returns K.  n = 0 gives K = 0.  FP64 sums in a fixed order:
- *  bitwise reproducible.  Errors: INVALID_ARG (d, n, h, max_iter, NULL
+ *  and the call returns K.  n = 0 gives K = 0.  FP64 sums in a fixed order
+ *  (one wave per seed, or four when there are at most 16,384 seeds; the
+ *  order depends only on the cells of a neighbourhood): modes, weights and
+ *  K are bitwise reproducible; the number of merge rounds may differ
+ *  between calls (a round can see decisions made earlier in the same
+ *  round).  Errors: INVALID_ARG (d, n, h, max_iter, NULL
  *  pointers, bin range), NONFINITE (a NaN or Inf coordinate), OOM, DEVICE. */
 typedef struct {
     int64_t n_seeds;    /* occupied bins */
     int32_t n_modes;    /* K */
-    int32_t rounds;     /* merge rounds until every mode was decided */
+    int32_t rounds;     /* merge rounds until every mode was decided (may vary) */
     int32_t max_iters;  /* the largest iteration count of a seed */
 } gmm_meanshift_info;
 size_t gmm_meanshift_workspace_size(int64_t n, int32_t d);
