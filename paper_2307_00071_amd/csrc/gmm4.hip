@@ -164,7 +164,9 @@ bool cull4_enabled() {
 bool make_cull4(int K, int64_t n, CullCfg4 *c) {
   const int cus = device_cus();
   if (cus <= 0 || K < 1 || K > kMaxK) return false;
-  c->scap = std::min(K, kCull4Cap);
+  // E rows: 128, or 256 above K = 256, where the FP64 sums leave LDS for
+  // one block per CU either way
+  c->scap = std::min(K, K > 256 ? 2 * kCull4Cap : kCull4Cap);
   c->nw = kCull4Waves;
   c->lds = cull4_lds(K, c->scap, c->nw).total;
   c->kfn = reinterpret_cast<const void *>(&em4_cull_kernel<kCull4Waves>);
