@@ -2038,8 +2038,9 @@ gmm_status gmm_fit_batched(int32_t B, const float *pts, const int64_t *pt_off,
 // ------------------------------------------------------- k-means++ seeding
 
 struct KppLayout {
-  size_t status, D, T, total;
+  size_t status, D, T, D2, T2, total;
   int64_t nch;
+  bool fused;   // one launch per round (double-buffered D, T)
 };
 
 KppLayout kpp_layout(int64_t n) {
@@ -2049,6 +2050,12 @@ KppLayout kpp_layout(int64_t n) {
   L.status = o; o = align256(o + sizeof(uint32_t));
   L.D = o; o = align256(o + (size_t)n * sizeof(double));
   L.T = o; o = align256(o + (size_t)L.nch * sizeof(double));
+  L.fused = L.nch <= kKppFuseChunks;
+  L.D2 = L.T2 = 0;
+  if (L.fused) {
+    L.D2 = o; o = align256(o + (size_t)n * sizeof(double));
+    L.T2 = o; o = align256(o + (size_t)L.nch * sizeof(double));
+  }
   L.total = o;
   return L;
 }
@@ -2078,15 +2085,30 @@ gmm_status gmm_kmeanspp(const float *pts, int64_t n, int32_t k, const double *u,
   hipLaunchKernelGGL(kpp_first_kernel, dim3(1), dim3(256), 0, s, u, k, n, centres,
                      status);
   HIP_TRY(hipGetLastError());
-  for (int j = 1; j < k; ++j) {
-    hipLaunchKernelGGL(kpp_update_kernel,
-                       dim3((unsigned)((L.nch + kKppUpdChunks - 1) / kKppUpdChunks)),
-                       dim3(kKppUpdThreads), 0, s, pts, n, centres, j - 1, D, T, L.nch,
-                       status);
+  const dim3 ugrid((unsigned)((L.nch + kKppUpdChunks - 1) / kKppUpdChunks));
+  if (L.fused && k >= 2) {
+    // round j: centre j from buffer (j - 1) & 1, distances into buffer j & 1
+    double *Db[2] = {D, at<double>(ws, L.D2)}, *Tb[2] = {T, at<double>(ws, L.T2)};
+    hipLaunchKernelGGL(kpp_update_kernel, ugrid, dim3(kKppUpdThreads), 0, s, pts, n, centres, 0,
+                       Db[0], Tb[0], L.nch, status);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(kpp_select_kernel, dim3(1), dim3(kKppSelThreads), 0, s, D, T, n, u, j,
-                       centres);
+    for (int j = 1; j + 1 < k; ++j) {
+      hipLaunchKernelGGL(kpp_round_kernel, ugrid, dim3(kKppUpdThreads), 0, s, pts, n, u, j,
+                         centres, Db[(j - 1) & 1], Tb[(j - 1) & 1], Db[j & 1], Tb[j & 1], L.nch);
+      HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(kpp_select_kernel, dim3(1), dim3(kKppSelThreads), 0, s, Db[k & 1],
+                       Tb[k & 1], n, u, k - 1, centres);
     HIP_TRY(hipGetLastError());
+  } else {
+    for (int j = 1; j < k; ++j) {
+      hipLaunchKernelGGL(kpp_update_kernel, ugrid, dim3(kKppUpdThreads), 0, s, pts, n, centres,
+                         j - 1, D, T, L.nch, status);
+      HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL(kpp_select_kernel, dim3(1), dim3(kKppSelThreads), 0, s, D, T, n, u, j,
+                         centres);
+      HIP_TRY(hipGetLastError());
+    }
   }
   if (!labels && k == 1) {  // no distances formed: check the points alone
     hipLaunchKernelGGL(kpp_check_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,

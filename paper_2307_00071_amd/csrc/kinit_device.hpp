@@ -117,12 +117,12 @@ __global__ __launch_bounds__(kKppUpdThreads) void kpp_update_kernel(
 // zero entries, so none of them is ever the first above a level); where
 // rounding leaves no entry above t, the last positive entry.
 constexpr int kKppSelPer = 16;
-constexpr int64_t kKppSelStage = (int64_t)kKppSelThreads * kKppSelPer;
 
-// Exclusive prefix of v over the block and the block total (*tot).  wtot:
-// kKppSelThreads / 64 + 1 doubles of LDS.  Three barriers.
+// Exclusive prefix of v over a block of NT threads and the block total
+// (*tot).  wtot: NT / 64 + 1 doubles of LDS.  Three barriers.
+template <int NT>
 __device__ __forceinline__ double kpp_block_scan(double v, double *wtot, double *tot) {
-  constexpr int NWV = kKppSelThreads / 64;
+  constexpr int NWV = NT / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double s = v;
   for (int off = 1; off < 64; off <<= 1) {
@@ -159,28 +159,32 @@ __device__ __forceinline__ void kpp_wave_mark(long long a, long long l,
   if (lb && lane == 63 - __builtin_clzll(lb)) atomicMax(lastp, l);
 }
 
-__global__ __launch_bounds__(kKppSelThreads) void kpp_select_kernel(
-    const double *__restrict__ D, const double *__restrict__ T, int64_t n,
-    const double *__restrict__ u, int j, int64_t *__restrict__ cidx) {
-  __shared__ double wtot[kKppSelThreads / 64 + 1];
+// The pick of one round by a block of NT threads (all of them call it; all
+// get the index): D the n squared distances, T their chunk totals; prev
+// is returned when W is not positive.
+template <int NT>
+__device__ int64_t kpp_pick(const double *__restrict__ D, const double *__restrict__ T,
+                            int64_t n, double uj, int64_t prev) {
+  constexpr int64_t STAGE = (int64_t)NT * kKppSelPer;
+  static_assert(NT >= kKppChunk, "a block covers a chunk");
+  __shared__ double wtot[NT / 64 + 1];
   __shared__ unsigned long long hit;   // smallest index above t (~0: none)
   __shared__ long long lastp;          // largest positive index (-1: none)
   __shared__ double hbefore, lbefore;  // running sum before the hit / last
+  __shared__ int64_t result;
   const int tid = threadIdx.x;
   const int64_t nch = (n + kKppChunk - 1) / kKppChunk;
-  const int64_t nst = (nch + kKppSelStage - 1) / kKppSelStage;
-  double uj = u[j];
-  if (!(uj >= 0.0 && uj < 1.0)) uj = 0.0;  // reported by kpp_first_kernel
+  const int64_t nst = (nch + STAGE - 1) / STAGE;
   double v[kKppSelPer];
   double off = 0.0, stot = 0.0;
   auto stage = [&](int64_t st) {   // v, this thread's offset in the stage, the stage total
-    const int64_t c0 = st * kKppSelStage + (int64_t)tid * kKppSelPer;
+    const int64_t c0 = st * STAGE + (int64_t)tid * kKppSelPer;
 #pragma unroll
     for (int q = 0; q < kKppSelPer; ++q) v[q] = (c0 + q < nch) ? T[c0 + q] : 0.0;
     double sum = 0.0;
 #pragma unroll
     for (int q = 0; q < kKppSelPer; ++q) sum += v[q];
-    off = kpp_block_scan(sum, wtot, &stot);
+    off = kpp_block_scan<NT>(sum, wtot, &stot);
   };
   // W: the stage totals in order
   double W = 0.0;
@@ -188,10 +192,7 @@ __global__ __launch_bounds__(kKppSelThreads) void kpp_select_kernel(
     stage(st);
     W += stot;
   }
-  if (!(W > 0.0)) {
-    if (tid == 0) cidx[j] = cidx[j - 1];
-    return;
-  }
+  if (!(W > 0.0)) return prev;   // uniform
   const double t = uj * W;
   // the chunk: first positive chunk total whose running sum exceeds t
   int64_t c = -1, cl = -1;
@@ -226,12 +227,12 @@ __global__ __launch_bounds__(kKppSelThreads) void kpp_select_kernel(
     if (myl >= 0 && myl == lastp) lbefore = mlb;
     __syncthreads();
     if (hit != ~0ull) {
-      c = st * kKppSelStage + (int64_t)hit;
+      c = st * STAGE + (int64_t)hit;
       cbefore = hbefore;
       break;
     }
     if (lastp >= 0) {
-      cl = st * kKppSelStage + lastp;
+      cl = st * STAGE + lastp;
       clbefore = lbefore;
     }
     base += stot;
@@ -240,15 +241,12 @@ __global__ __launch_bounds__(kKppSelThreads) void kpp_select_kernel(
     c = cl;
     cbefore = clbefore;
   }
-  if (c < 0) {  // a guard: W > 0 has a positive chunk
-    if (tid == 0) cidx[j] = cidx[j - 1];
-    return;
-  }
+  if (c < 0) return prev;   // a guard: W > 0 has a positive chunk
   // the point: first positive D2 of chunk c whose running sum exceeds t
   const int64_t i0 = c * kKppChunk;
   const double x = (tid < kKppChunk && i0 + tid < n) ? D[i0 + tid] : 0.0;
   double ctot = 0.0;
-  const double pre = cbefore + kpp_block_scan(x, wtot, &ctot);
+  const double pre = cbefore + kpp_block_scan<NT>(x, wtot, &ctot);
   __syncthreads();
   if (tid == 0) {
     hit = ~0ull;
@@ -260,7 +258,68 @@ __global__ __launch_bounds__(kKppSelThreads) void kpp_select_kernel(
   __syncthreads();
   if (tid == 0) {
     const long long p = hit != ~0ull ? (long long)hit : lastp;
-    cidx[j] = p >= 0 ? i0 + p : cidx[j - 1];
+    result = p >= 0 ? i0 + p : prev;
+  }
+  __syncthreads();
+  return result;
+}
+
+__device__ __forceinline__ double kpp_draw(const double *__restrict__ u, int j) {
+  const double uj = u[j];
+  return (uj >= 0.0 && uj < 1.0) ? uj : 0.0;  // reported by kpp_first_kernel
+}
+
+__global__ __launch_bounds__(kKppSelThreads) void kpp_select_kernel(
+    const double *__restrict__ D, const double *__restrict__ T, int64_t n,
+    const double *__restrict__ u, int j, int64_t *__restrict__ cidx) {
+  const int64_t c = kpp_pick<kKppSelThreads>(D, T, n, kpp_draw(u, j), cidx[j - 1]);
+  if (threadIdx.x == 0) cidx[j] = c;
+}
+
+// One whole round j >= 1 for clouds of at most kKppFuseChunks chunks:
+// every block picks centre j from the distances and chunk totals of round
+// j - 1 (Dp, Tp; the same result in every block, written by block 0), then
+// forms the distances to it (min with Dp) and the chunk totals of its own
+// chunks into Dn, Tn, as kpp_update_kernel does.  Double buffers: no block
+// writes what another may still read, and no synchronisation between
+// blocks is needed.
+constexpr int64_t kKppFuseChunks = (int64_t)kKppUpdThreads * kKppSelPer;
+__global__ __launch_bounds__(kKppUpdThreads) void kpp_round_kernel(
+    const float *__restrict__ pts, int64_t n, const double *__restrict__ u, int j,
+    int64_t *__restrict__ cidx, const double *__restrict__ Dp, const double *__restrict__ Tp,
+    double *__restrict__ Dn, double *__restrict__ Tn, int64_t nch) {
+  __shared__ double sh[kKppUpdChunks * kKppRow];
+  const int64_t c = kpp_pick<kKppUpdThreads>(Dp, Tp, n, kpp_draw(u, j), cidx[j - 1]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) cidx[j] = c;
+  const double c0 = pts[3 * c], c1 = pts[3 * c + 1], c2 = pts[3 * c + 2];
+  const int64_t base = (int64_t)blockIdx.x * kKppUpdChunks * kKppChunk;
+  constexpr int PER = kKppUpdChunks * kKppChunk / kKppUpdThreads;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int l = q * kKppUpdThreads + threadIdx.x;
+    const int64_t i = base + l;
+    double v = 0.0;  // past the end: 0, which leaves the running sums as they are
+    if (i < n) {
+      const double d = kpp_d2(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2], c0, c1, c2);
+      const double o = Dp[i];
+      v = d < o ? d : o;
+      Dn[i] = v;
+    }
+    sh[(l / kKppChunk) * kKppRow + (l % kKppChunk)] = v;
+  }
+  __syncthreads();
+  const int64_t ch = (int64_t)blockIdx.x * kKppUpdChunks + threadIdx.x;
+  if (threadIdx.x < kKppUpdChunks && ch < nch) {
+    const double *a = sh + threadIdx.x * kKppRow;
+    double s = 0.0;
+    for (int k0 = 0; k0 < kKppChunk; k0 += 16) {
+      double e[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) e[k] = a[k0 + k];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s += e[k];
+    }
+    Tn[ch] = s;
   }
 }
 
