@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "d2d_device.hpp"
 #include "gmm.h"
@@ -148,6 +149,111 @@ gmm_status get_ws(void **ws, size_t *ws_bytes, size_t need, hipStream_t s, WsGua
 
 }  // namespace
 
+namespace {
+
+// ---- gmm_d2d_register: the launches, and graphs of repeated calls
+struct Reg {
+  const double *T0;
+  const float *w, *mu, *cov, *tw, *tmu, *tcov;
+  double *T_out, *history;
+  int32_t *counts;
+  void *ws;
+  size_t ws_bytes;
+  int32_t m, n, iters_iso, iters_aniso;
+  int dev;
+  bool operator==(const Reg &o) const {
+    return T0 == o.T0 && w == o.w && mu == o.mu && cov == o.cov && tw == o.tw &&
+           tmu == o.tmu && tcov == o.tcov && T_out == o.T_out && history == o.history &&
+           counts == o.counts && ws == o.ws && ws_bytes == o.ws_bytes && m == o.m &&
+           n == o.n && iters_iso == o.iters_iso && iters_aniso == o.iters_aniso &&
+           dev == o.dev;
+  }
+};
+
+gmm_status reg_enqueue(const Reg &r, const D2DLayout &L, hipStream_t s) {
+  void *ws = r.ws;
+  const int m = r.m, n = r.n;
+  const float *w = r.w, *mu = r.mu, *cov = r.cov, *tw = r.tw, *tmu = r.tmu, *tcov = r.tcov;
+  double *history = r.history, *T_out = r.T_out;
+  int32_t *counts = r.counts;
+  const double *T0 = r.T0;
+  const int iters_iso = r.iters_iso, iters_aniso = r.iters_aniso;
+  gmm_status e;
+  State *st = at<State>(ws, L.state);
+  const int hist_len = iters_iso + iters_aniso + 2;
+  hipLaunchKernelGGL(d2d_init_kernel, dim3(1), dim3(256), 0, s, st, T0, (const double *)nullptr,
+                     history, history ? hist_len : 0, counts);
+  HIP_TRY(hipGetLastError());
+  const int iters[2] = {iters_iso, iters_aniso};
+  for (int stage = 0; stage < 2; ++stage) {
+    if (iters[stage] == 0) continue;
+    if ((e = prep(ws, L, m, w, mu, cov, n, tw, tmu, tcov, stage == 0, s)) != GMM_OK) return e;
+    hipLaunchKernelGGL(d2d_stage_kernel, dim3(1), dim3(64), 0, s, st, stage);
+    HIP_TRY(hipGetLastError());
+    if ((e = value(ws, L, m, n, 0, 1, s)) != GMM_OK) return e;
+    hipLaunchKernelGGL(d2d_take_f_kernel, dim3(1), dim3(64), 0, s, st, history, hist_len);
+    HIP_TRY(hipGetLastError());
+    for (int it = 0; it < iters[stage]; ++it) {
+      if ((e = stats_step(ws, L, m, n, nullptr, nullptr, s)) != GMM_OK) return e;
+      if ((e = value(ws, L, m, n, 1, kTrials, s)) != GMM_OK) return e;
+      hipLaunchKernelGGL(d2d_accept_kernel, dim3(1), dim3(64), 0, s, st, history, hist_len);
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  hipLaunchKernelGGL(d2d_out_kernel, dim3(1), dim3(64), 0, s, st, T_out, counts);
+  HIP_TRY(hipGetLastError());
+  return GMM_OK;
+}
+
+struct RegEntry {
+  bool used = false;
+  Reg key{};
+  hipGraphExec_t exec = nullptr;
+  uint64_t stamp = 0;
+};
+constexpr int kRegSlots = 8;
+std::mutex g_reg_mu;
+RegEntry g_reg[kRegSlots];
+uint64_t g_reg_clock = 0;
+
+bool reg_graphs_enabled() {
+  const char *e = getenv("GMM_GRAPHS");
+  return !(e && e[0] == '0');
+}
+
+hipStream_t reg_capture_stream() {
+  thread_local hipStream_t cs[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  if (!cs[dev] && hipStreamCreateWithFlags(&cs[dev], hipStreamNonBlocking) != hipSuccess)
+    cs[dev] = nullptr;
+  return cs[dev];
+}
+
+RegEntry *reg_slot(const Reg &key, bool *found) {
+  RegEntry *victim = &g_reg[0];
+  for (auto &e : g_reg) {
+    if (e.used && e.key == key) {
+      *found = true;
+      e.stamp = ++g_reg_clock;
+      return &e;
+    }
+    if (!e.used || (victim->used && e.stamp < victim->stamp)) victim = &e;
+  }
+  *found = false;
+  if (victim->exec) {
+    (void)hipDeviceSynchronize();  // an evicted graph may still be running
+    (void)hipGraphExecDestroy(victim->exec);
+  }
+  *victim = RegEntry{};
+  victim->used = true;
+  victim->key = key;
+  victim->stamp = ++g_reg_clock;
+  return victim;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t gmm_d2d_workspace_size(int32_t m, int32_t n) {
@@ -198,30 +304,35 @@ gmm_status gmm_d2d_register(const double *T0, int32_t m, const float *w, const f
   const D2DLayout L = d2d_layout(m, n);
   WsGuard guard;
   if ((e = get_ws(&ws, &ws_bytes, L.total, s, &guard)) != GMM_OK) return e;
-  State *st = at<State>(ws, L.state);
-  const int hist_len = iters_iso + iters_aniso + 2;
-  hipLaunchKernelGGL(d2d_init_kernel, dim3(1), dim3(256), 0, s, st, T0, (const double *)nullptr,
-                     history, history ? hist_len : 0, counts);
-  HIP_TRY(hipGetLastError());
-  const int iters[2] = {iters_iso, iters_aniso};
-  for (int stage = 0; stage < 2; ++stage) {
-    if (iters[stage] == 0) continue;
-    if ((e = prep(ws, L, m, w, mu, cov, n, tw, tmu, tcov, stage == 0, s)) != GMM_OK) return e;
-    hipLaunchKernelGGL(d2d_stage_kernel, dim3(1), dim3(64), 0, s, st, stage);
-    HIP_TRY(hipGetLastError());
-    if ((e = value(ws, L, m, n, 0, 1, s)) != GMM_OK) return e;
-    hipLaunchKernelGGL(d2d_take_f_kernel, dim3(1), dim3(64), 0, s, st, history, hist_len);
-    HIP_TRY(hipGetLastError());
-    for (int it = 0; it < iters[stage]; ++it) {
-      if ((e = stats_step(ws, L, m, n, nullptr, nullptr, s)) != GMM_OK) return e;
-      if ((e = value(ws, L, m, n, 1, kTrials, s)) != GMM_OK) return e;
-      hipLaunchKernelGGL(d2d_accept_kernel, dim3(1), dim3(64), 0, s, st, history, hist_len);
-      HIP_TRY(hipGetLastError());
+  const Reg key{T0, w, mu, cov, tw, tmu, tcov, T_out, history, counts, ws, ws_bytes, m, n,
+                iters_iso, iters_aniso, 0};
+  // repeated calls with the same arguments replay a captured graph (the
+  // first runs directly, the second captures); not with a temporary workspace
+  if (reg_graphs_enabled() && !guard.ptr) {
+    Reg k2 = key;
+    (void)hipGetDevice(&k2.dev);
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    bool found = false;
+    RegEntry *ent = reg_slot(k2, &found);
+    if (found && !ent->exec) {
+      hipStream_t cs = reg_capture_stream();
+      if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        const gmm_status cst = reg_enqueue(key, L, cs);
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &g);
+        if (cst == GMM_OK && ee == hipSuccess && g &&
+            hipGraphInstantiate(&ent->exec, g, nullptr, nullptr, 0) != hipSuccess)
+          ent->exec = nullptr;
+        if (g) (void)hipGraphDestroy(g);
+      }
+      (void)hipGetLastError();
+    }
+    if (ent->exec) {
+      HIP_TRY(hipGraphLaunch(ent->exec, s));
+      return GMM_OK;
     }
   }
-  hipLaunchKernelGGL(d2d_out_kernel, dim3(1), dim3(64), 0, s, st, T_out, counts);
-  HIP_TRY(hipGetLastError());
-  return GMM_OK;
+  return reg_enqueue(key, L, s);
 }
 
 }  // extern "C"
