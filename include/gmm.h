@@ -125,10 +125,20 @@ gmm_status gmm_workspace_status(const void *ws, void *stream);
  *  dense evaluation up to the order of FP32 additions; the caller's arrays are not reordered, and repeated calls
  *  with the same inputs give bitwise identical results.  GMM_CULL=0 or
  *  GMM_SORT=0 in the environment switch the skipping or the ordering off.
+ *  Small fits (K <= 16, N <= 65,536 and at most one 256-point tile per
+ *  compute unit, shifted moments) skip the ordering and run all soft
+ *  iterations in one launch: one block per tile, a device-wide barrier per
+ *  iteration, and every block adds all partial rows in the same order and
+ *  makes the same FP64 M-step, so the results are again bitwise
+ *  reproducible (they differ from the launch-per-pass form in the order of
+ *  additions only; GMM_SMALL=0 selects that form).  The barrier waits are
+ *  bounded: a block that waits too long gives up, every block exits and
+ *  the call returns GMM_ERR_DEVICE.
  *  Synchronises `stream` once at the end unless GMM_FLAG_ASYNC is set.
  *  Errors: INVALID_ARG (sizes, NULL pointers, options), UNSUPPORTED
  *  (K > GMM_MAX_K), OOM (workspace), then device-side NOT_SPD / NONFINITE /
- *  INVALID_ARG (label out of range). */
+ *  INVALID_ARG (label out of range), DEVICE (a one-launch fit's barrier
+ *  gave up, e.g. when other work kept its blocks from being resident). */
 size_t gmm_fit_workspace_size(int64_t n, int32_t k, const gmm_fit_opts *opts);
 
 gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,

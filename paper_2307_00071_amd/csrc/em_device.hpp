@@ -235,6 +235,38 @@ __device__ inline double block_max_fast(double v, double *scratch) {
   return scratch[NT / 64];
 }
 
+// FP64 reductions over the 16 lanes of a DPP row (mirror, half-mirror,
+// xor 2, xor 1 exchanges): every lane of the row ends with the same bits,
+// as each exchange adds the same two values on both sides.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_f64<0x140>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x4E>(v);
+  return v + dpp_f64<0xB1>(v);
+}
+__device__ __forceinline__ double row16_max(double v) {
+  v = fmax(v, dpp_f64<0x140>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  return fmax(v, dpp_f64<0xB1>(v));
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+// The sum over a wave: the four row sums added in row order (wave-uniform).
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v = row16_sum(v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) +
+         (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 // ------------------------------------------------------------------ M-step
 // From the reduced statistics tot[] (column s*K + b: N0, S1 (3), S2 (6); the
 // log-likelihood at 10 K) and the shift m the tile kernel subtracted:
@@ -243,8 +275,10 @@ __device__ inline double block_max_fast(double v, double *scratch) {
 // which is sum g (x - mu)(x - mu)^T / N_b + lambda I exactly;
 //   pi_b = N_b / sum_a N_a, then the eq. 3 terms for the next E-step.
 // One block of NT >= K threads, thread b owns component b (registers only);
-// scratch holds 2 NT / 64 doubles.
-template <int NT>
+// scratch holds 2 NT / 64 doubles.  ROW16 (K <= 16: every component in the
+// first DPP row): sum N_b and max cb by a row reduction, no scratch and no
+// barrier.
+template <int NT, bool ROW16 = false>
 __device__ __forceinline__ void em_update_block(const double *tot, int K, int umode, double reg,
                                 const float *cpar_in, const float4 *shift_in,
                                 float *cpar_out, float4 *shift_out,
@@ -305,21 +339,28 @@ __device__ __forceinline__ void em_update_block(const double *tot, int K, int um
   if (act && chol_inv3(C, P)) cb = log(Nb * P[0] * P[2] * P[5]);
   if (act && !isfinite(cb)) set_status(status, kStNotSpd);
   double sN = act ? Nb : 0.0, mC = cb;
-  for (int off = 32; off > 0; off >>= 1) {
-    sN += __shfl_xor(sN, off, 64);
-    mC = fmax(mC, __shfl_xor(mC, off, 64));
-  }
-  constexpr int NWV = NT / 64;
-  if ((b & 63) == 0) {
-    scratch[b >> 6] = sN;
-    scratch[NWV + (b >> 6)] = mC;
-  }
-  __syncthreads();
-  double Ntot = scratch[0], Mx = scratch[NWV];
+  double Ntot, Mx;
+  if constexpr (ROW16) {
+    Ntot = row16_sum(sN);
+    Mx = row16_max(mC);
+  } else {
+    for (int off = 32; off > 0; off >>= 1) {
+      sN += __shfl_xor(sN, off, 64);
+      mC = fmax(mC, __shfl_xor(mC, off, 64));
+    }
+    constexpr int NWV = NT / 64;
+    if ((b & 63) == 0) {
+      scratch[b >> 6] = sN;
+      scratch[NWV + (b >> 6)] = mC;
+    }
+    __syncthreads();
+    Ntot = scratch[0];
+    Mx = scratch[NWV];
 #pragma unroll
-  for (int j = 1; j < NWV; ++j) {
-    Ntot += scratch[j];
-    Mx = fmax(Mx, scratch[NWV + j]);
+    for (int j = 1; j < NWV; ++j) {
+      Ntot += scratch[j];
+      Mx = fmax(Mx, scratch[NWV + j]);
+    }
   }
   if (act) {
     double *t = th64 + (size_t)b * kTh64Stride;

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "em_device.hpp"
+#include "small_fit_device.hpp"
 #include "order_device.hpp"
 #include "kinit_device.hpp"
 #include "gmm.h"
@@ -560,7 +561,9 @@ WsLayout ws_layout(int64_t n, int K, const TileCfg &c, int extra_cols = 0,
   L.nslots = std::max(std::max(c.grid, grid_override), max_grid(K, n));
   L.npad = ((n + 255) / 256) * 256;   // a multiple of every tile size
   L.status = o; o = align256(o + 256);
-  L.counter = o; o = align256(o + 4 * sizeof(unsigned));   // stopping rule state
+  // stopping rule state (words 0-3), the one-launch fit's grid barrier
+  // ticket and give-up flag (words 4, 5)
+  L.counter = o; o = align256(o + 8 * sizeof(unsigned));
   L.pose64 = o; o = align256(o + 32 * sizeof(double));
   L.rt32 = o; o = align256(o + 16 * sizeof(float));
   for (int i = 0; i < 2; ++i) {
@@ -596,6 +599,7 @@ gmm_status status_from_bits(uint32_t bits) {
   if (bits & kStBadArg) return fail(GMM_ERR_INVALID_ARG, "device: invalid label or parameter");
   if (bits & kStNotSpd) return fail(GMM_ERR_NOT_SPD, "device: covariance not SPD");
   if (bits & kStNonFinite) return fail(GMM_ERR_NONFINITE, "device: non-finite value");
+  if (bits & kStDevice) return fail(GMM_ERR_DEVICE, "device: the one-launch fit's grid barrier gave up");
   return GMM_OK;
 }
 
@@ -654,6 +658,7 @@ struct Run {
   int64_t n = 0;             // points
   bool fused = false;        // lambda > 0: one reduce + update launch per pass
   int conv_par = 0;          // which flag word holds the current stopping state
+  bool small = false;        // soft iterations in one launch (em_small_fit_kernel)
 };
 
 // The tile kernel alone (writes the partial rows only).
@@ -834,7 +839,7 @@ gmm_status run_pass(Run &r, int mode, int umode, double reg, double *loglik_slot
 gmm_status run_init(Run &r, bool zero_shift) {
   hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, r.s,
                      at<uint32_t>(r.ws, r.L.status),
-                     at<unsigned>(r.ws, r.L.counter), 4,
+                     at<unsigned>(r.ws, r.L.counter), 8,
                      zero_shift ? at<float4>(r.ws, r.L.shift[r.cur]) : nullptr,
                      r.K);
   HIP_TRY(hipGetLastError());
@@ -926,6 +931,55 @@ gmm_status finish(Run &r, bool sync) {
   return status_from_bits(bits);
 }
 
+// Fits with K <= 16 components and at most 256 tiles of 256 points (and
+// no more tiles than compute units) with shifted moments run their soft
+// iterations in one launch of em_small_fit_kernel: one block per tile, all
+// resident at once.  GMM_SMALL=0, or a tile shape forced by GMM_TILE_SHAPE,
+// keeps a launch pair per iteration.
+int small_give_up() {
+  const char *e = getenv("GMM_SMALL_TEST_GIVE_UP");
+  return e ? atoi(e) : -1;
+}
+
+bool small_fit_ok(int K, const WsLayout &L, const gmm_fit_opts *opts) {
+  const char *e = getenv("GMM_SMALL");
+  if ((e && e[0] == '0') || getenv("GMM_TILE_SHAPE")) return false;
+  const int64_t nt = L.npad / kSmallThreads;
+  return K <= kSmallMaxK && nt <= kSmallMaxTiles && nt <= dev_info().cus &&
+         2 * nt <= L.nslots && opts->moment_mode == GMM_MOMENTS_SHIFTED &&
+         opts->iters > 0;
+}
+
+// The soft iterations of a small fit: parameters cur -> 1 - cur, the
+// log-likelihood of iteration t into loglik[t].
+gmm_status run_small(Run &r, int iters, double reg, double *loglik) {
+  const WsLayout &L = r.L;
+  SmallArgs a;
+  a.K = r.K;
+  int P = 1;   // point subsets: the largest power of two with P K <= 256
+  while (2 * P * r.K <= kSmallThreads) P *= 2;
+  a.P = P;
+  a.trip = kSmallThreads / P;
+  a.iters = iters;
+  a.ncols = L.ncols;
+  a.reg = reg;
+  a.tol_abs = r.tol_abs;
+  // GMM_SMALL_TEST_GIVE_UP=t: block 0 gives up at the barrier of iteration t
+  // (tests of the error path; every block still exits)
+  a.give_up_at = small_give_up();
+  const int grid = (int)(L.npad / kSmallThreads);
+  const int nxt = 1 - r.cur;
+  hipLaunchKernelGGL(em_small_fit_kernel, dim3(grid), dim3(kSmallThreads), 0, r.s,
+                     at<float4>(r.ws, L.pts4), at<float>(r.ws, L.cpar[r.cur]),
+                     at<float4>(r.ws, L.shift[r.cur]), at<float>(r.ws, L.cpar[nxt]),
+                     at<float4>(r.ws, L.shift[nxt]), at<double>(r.ws, L.th64),
+                     at<double>(r.ws, L.part), at<unsigned>(r.ws, L.counter) + 4,
+                     loglik, at<uint32_t>(r.ws, L.status), a);
+  HIP_TRY(hipGetLastError());
+  r.cur = nxt;
+  return GMM_OK;
+}
+
 // Every launch of one fit, in order.
 gmm_status enqueue_fit(Run &r, const float *pts, int64_t n,
                        const int32_t *init_labels, float *w, float *mu,
@@ -943,11 +997,13 @@ gmm_status enqueue_fit(Run &r, const float *pts, int64_t n,
   } else {
     if ((st = run_precompute(r, w, mu, cov)) != GMM_OK) return st;
   }
-  if (may_tune && !r.cull && autotune_on() && forced_candidate() < 0 &&
+  if (may_tune && !r.cull && !r.small && autotune_on() && forced_candidate() < 0 &&
       tuned_candidate(r.K, n) < 0 &&
       (st = autotune(r, n)) != GMM_OK)
     return st;
-  for (int t = 0; t < opts->iters; ++t) {
+  if (r.small) {
+    if ((st = run_small(r, opts->iters, reg, loglik)) != GMM_OK) return st;
+  } else for (int t = 0; t < opts->iters; ++t) {
     double *slot = loglik ? loglik + t : nullptr;
     if (opts->moment_mode == GMM_MOMENTS_TWO_PASS) {
       if ((st = run_pass(r, kSoftStats, kUpdMeanOnly, reg, slot, nullptr)) != GMM_OK) return st;
@@ -990,6 +1046,11 @@ gmm_status fit_setup(const float *pts, int64_t n, int32_t k, const float *w,
   r->cull = pick_cull_cfg(k, n, &r->cc);
   if (r->cull) debug_cfg("fit", k, n, r->cc.name, r->cc.grid, r->cc.block, r->cc.lds);
   r->L = ws_layout(n, k, r->c, 0, 0, true);
+  // a one-launch fit runs its label and final passes dense: the spatial
+  // order and the tile spheres of culling would cost more than they save.
+  // Profiled fits (per-pass tile timing) keep the launch pairs.
+  r->small = g_prof.reps == 0 && small_fit_ok(k, r->L, opts);
+  if (r->small) r->cull = false;
   r->s = static_cast<hipStream_t>(stream);
   return GMM_OK;
 }
@@ -1006,14 +1067,15 @@ struct FitKey {
   double reg, tol;
   int k, iters, mode, dev;
   const void *dense, *culled;  // the kernels the fit launches
-  bool sorted, fused;
+  bool sorted, fused, small;
+  int give_up;   // GMM_SMALL_TEST_GIVE_UP (a launch argument)
   bool operator==(const FitKey &o) const {
     return pts == o.pts && labels == o.labels && w == o.w && mu == o.mu &&
            cov == o.cov && loglik == o.loglik && ws == o.ws && n == o.n &&
            ws_bytes == o.ws_bytes && reg == o.reg && tol == o.tol && k == o.k &&
            iters == o.iters && mode == o.mode && dev == o.dev &&
            dense == o.dense && culled == o.culled && sorted == o.sorted &&
-           fused == o.fused;
+           fused == o.fused && small == o.small && give_up == o.give_up;
   }
 };
 
@@ -1776,7 +1838,7 @@ gmm_status gmm_fit(const float *pts, int64_t n, int32_t k,
                opts->reg_covar, opts->tol, k, opts->iters, opts->moment_mode, 0,
                reinterpret_cast<const void *>(r.c.launch),
                r.cull ? reinterpret_cast<const void *>(r.cc.launch) : nullptr,
-               sort_enabled(), r.fused};
+               sort_enabled(), r.fused, r.small, small_give_up()};
     (void)hipGetDevice(&key.dev);
     std::lock_guard<std::mutex> lk(g_graph_mu);
     bool found = false;

@@ -585,3 +585,99 @@ def test_tolerance_stops_early_like_a_shorter_fit(mode):
     assert L[T] == Ls[t_star + 1]
     with pytest.raises(_lib.GmmError):
         gmm.fit(_to(X), K, iters=3, labels=_to(lab, torch.int32), tol=-1.0)
+
+
+# ------------------------------------------------- one-launch small fits
+# Fits with K <= 16 and at most 256 tiles of 256 points run every soft
+# iteration in one launch (one block per tile, a grid barrier per
+# iteration, every block reducing all partial rows the same way);
+# GMM_SMALL=0 keeps a launch pair per iteration.
+
+def _far_blobs():
+    """Blobs, the start theta fitted to them alone, and five points 1.5 km
+    away: at the first E-step every e_pb of those points underflows in FP32
+    and they take the exact max-shifted path."""
+    Xb = _blob_case(8, n_per=500)
+    lab = synth.kmeanspp_labels(Xb, 6, 1)
+    theta = _theta32(*oracle.fit(Xb, 6, 1e-3, 2, labels=lab)[:3])
+    far = np.array([[900.0, -900.0, 900.0]], np.float32) + \
+        np.random.default_rng(8).normal(scale=0.1, size=(5, 3)).astype(np.float32)
+    return np.ascontiguousarray(np.vstack([Xb, far])), theta
+
+
+@pytest.mark.parametrize("K,n", [(8, 10000), (1, 1000), (3, 777), (5, 257),
+                                 (6, "far"), (12, 40000), (16, 65536)])
+def test_one_launch_small_fit_matches_launch_pairs_and_oracle(K, n, monkeypatch):
+    """L at every iteration against the oracle (1e-4, floor N) and against
+    the launch-pair path (1e-5); means against the oracle (1e-4); a repeat
+    is bitwise equal; GMM_SMALL_TEST_GIVE_UP makes block 0 give up at a
+    barrier, which must end the launch with GMM_ERR_DEVICE (so the
+    one-launch kernel is the one that ran), and the next fit is clean."""
+    _case("one-launch small fit K=%d n=%s" % (K, n))
+    lab = theta = None
+    if n == "far":
+        X, theta = _far_blobs()
+    else:
+        X = _blob_case() if n == 10000 else _depth_subset(n, seed=K + 50)
+        lab = synth.kmeanspp_labels(X, K, 1)
+    N = X.shape[0]
+    T = 20
+
+    def run():
+        return _fit(X, K, T, labels=lab, theta0=theta)
+
+    monkeypatch.setenv("GMM_SMALL", "0")
+    L0 = run()[3]
+    monkeypatch.setenv("GMM_SMALL", "1")
+    w1, mu1, cov1, L1 = run()
+    wr, mur, covr, Lr = oracle.fit(X, K, 1e-3, T, labels=lab, theta0=theta)
+    err = np.abs(L1 - Lr) / np.maximum(np.abs(Lr), N)
+    dev = np.abs(L1 - L0) / np.maximum(np.abs(L0), N)
+    print("vs oracle %.2e, vs launch pairs %.2e" % (err.max(), dev.max()))
+    assert err.max() <= 1e-4
+    assert dev.max() <= 1e-5
+    assert _rel(mu1, mur) <= 1e-4
+    assert abs(w1.sum() - 1.0) <= 1e-5
+    monkeypatch.setenv("GMM_SMALL_TEST_GIVE_UP", "2")
+    with pytest.raises(_lib.GmmError) as e:
+        run()
+    assert e.value.status == 5
+    monkeypatch.delenv("GMM_SMALL_TEST_GIVE_UP")
+    w2, mu2, cov2, L2 = run()
+    np.testing.assert_array_equal(L2, L1)
+    np.testing.assert_array_equal(mu2, mu1)
+    np.testing.assert_array_equal(cov2, cov1)
+
+
+def test_one_launch_small_fit_one_step_parity():
+    """One E+M step from identical float32 parameters: the 1e-5 bar."""
+    _case("one-launch small fit one step")
+    X = _blob_case(4)
+    lab = synth.kmeanspp_labels(X, 8, 1)
+    theta = oracle.fit(X, 8, 1e-3, 2, labels=lab)[:3]
+    errs = _one_step(X, 8, theta)
+    print(errs)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_one_launch_small_fit_graph_replay():
+    """The blob fit repeated with identical buffers (direct, captured,
+    replayed): every call bitwise equal to the first."""
+    _case("one-launch small fit graph replay")
+    X = _blob_case()
+    lab = synth.kmeanspp_labels(X, 8, 1)
+    pts = _to(X)
+    labt = _to(lab, torch.int32)
+    ws = torch.empty(gmm.fit_workspace_bytes(X.shape[0], 8, 50), dtype=torch.uint8,
+                     device=DEV)
+    other = torch.randn(1 << 20, device=DEV)
+    outs = []
+    for i in range(4):
+        r = gmm.fit(pts, 8, iters=50, reg_covar=1e-3, labels=labt, workspace=ws)
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy().copy() for t in r])
+        float(other.sum())
+        torch.cuda.synchronize()
+    for o in outs[1:]:
+        for u, v in zip(outs[0], o):
+            np.testing.assert_array_equal(u, v)
