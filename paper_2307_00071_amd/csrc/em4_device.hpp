@@ -14,8 +14,11 @@
 #include <stdint.h>
 
 #include "gmm.h"
+#include "wave_f64.hpp"
 
 namespace gmm4_dev {
+
+using namespace gmm_wave;
 
 constexpr double kLog2e = 1.44269504088896340736;
 constexpr double kLn2 = 0.693147180559945309417;
@@ -438,11 +441,11 @@ __global__ __launch_bounds__(kUpdThreads) void update4_kernel(
 // near 0 for a typical weight 1/K; sum_a N_a = n + K eps (each point's
 // responsibilities sum to one).  So each component is updated on its own:
 // block b sums its 15 columns of the component-major partial rows (thread
-// (g, s) statistic s of rows g, g + G, ..., 16 loads in flight, then a
-// fixed pairwise tree over the G groups), thread 0 updates it in FP64; the
-// last wave of block 0 sums the log-likelihood column.  Bitwise
-// reproducible.
-constexpr int kFuse4Groups = 32;
+// (g, s) statistic s of rows g, g + G, ..., 16 loads in flight, then half
+// a wave per statistic adds the G group sums: DPP rows, then the two rows
+// in order), thread 0 updates it in FP64; the last wave of block 0 sums the
+// log-likelihood column.  Bitwise reproducible.
+constexpr int kFuse4Groups = 32;   // one per lane of a half wave
 constexpr int kFuse4Lwave = (kNStat * kFuse4Groups + 63) / 64 * 64;   // first thread of the L wave
 constexpr int kFuse4Threads = kFuse4Lwave + 64;
 
@@ -493,15 +496,18 @@ __global__ __launch_bounds__(kFuse4Threads) void reduce_update4_kernel(
 #pragma unroll
       for (int u = 0; u < 16; ++u) acc += v[u];
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    acc = wave_sum_f64(acc);
     if (lane == 0) tot[kNStat] = acc;
   }
-#pragma unroll
-  for (int half = kFuse4Groups / 2; half > 0; half >>= 1) {
-    __syncthreads();
-    if (stats && tid < half * kNStat) sums[tid] += sums[tid + half * kNStat];
+  // wave w adds the G = 32 group sums of statistics 2w (lanes 0-31) and
+  // 2w + 1 (lanes 32-63), lane g of a half holding group g
+  __syncthreads();
+  if (stats && 2 * (tid >> 6) < kNStat) {
+    const int w = tid >> 6, st = 2 * w + (lane >> 5);
+    const double2 h = half_sums_f64(st < kNStat ? sums[(lane & 31) * kNStat + st] : 0.0);
+    if (lane == 0) tot[2 * w] = h.x;
+    if (lane == 0 && 2 * w + 1 < kNStat) tot[2 * w + 1] = h.y;
   }
-  if (stats && tid < kNStat) tot[tid] = sums[tid];
   __syncthreads();
   if (tid != 0) return;
   if (lcol && loglik_slot) {

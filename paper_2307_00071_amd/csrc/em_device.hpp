@@ -23,8 +23,11 @@
 #include <stdint.h>
 
 #include "gmm.h"
+#include "wave_f64.hpp"
 
 namespace gmm_dev {
+
+using namespace gmm_wave;
 
 // ------------------------------------------------------------------ constants
 
@@ -233,38 +236,6 @@ __device__ inline double block_max_fast(double v, double *scratch) {
   }
   __syncthreads();
   return scratch[NT / 64];
-}
-
-// FP64 reductions over the 16 lanes of a DPP row (mirror, half-mirror,
-// xor 2, xor 1 exchanges): every lane of the row ends with the same bits,
-// as each exchange adds the same two values on both sides.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double row16_sum(double v) {
-  v += dpp_f64<0x140>(v);
-  v += dpp_f64<0x141>(v);
-  v += dpp_f64<0x4E>(v);
-  return v + dpp_f64<0xB1>(v);
-}
-__device__ __forceinline__ double row16_max(double v) {
-  v = fmax(v, dpp_f64<0x140>(v));
-  v = fmax(v, dpp_f64<0x141>(v));
-  v = fmax(v, dpp_f64<0x4E>(v));
-  return fmax(v, dpp_f64<0xB1>(v));
-}
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
-                          __builtin_amdgcn_readlane(__double2loint(v), lane));
-}
-// The sum over a wave: the four row sums added in row order (wave-uniform).
-__device__ __forceinline__ double wave_sum_f64(double v) {
-  v = row16_sum(v);
-  return (readlane_f64(v, 0) + readlane_f64(v, 16)) +
-         (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 // ------------------------------------------------------------------ M-step
@@ -1630,12 +1601,13 @@ __device__ __forceinline__ void update_body(const UpdPtrs &q, const UpdArgs &a,
 // adjacent), and one block per component sums its ten columns over the
 // rows and updates it in FP64: thread (g, s) takes statistic s of the rows
 // g, g + G, g + 2G, ...
-// (G = kFuseGroups, added in row order), the G group sums are added by a
-// fixed pairwise tree; block 0's last wave also sums the log-likelihood
-// column (lane l the rows l, l + 64, ..., then a fixed butterfly).  One
-// launch instead of reduce_rows_kernel + update_kernel, bitwise
-// reproducible.
+// (G = kFuseGroups, added in row order), wave s adds the G group sums of
+// statistic s (DPP row sums, then the four rows in order); block 0's last
+// wave also sums the log-likelihood column (lane l the rows l, l + 64,
+// ..., then the same wave sum).  One launch instead of reduce_rows_kernel
+// + update_kernel, bitwise reproducible.
 constexpr int kFuseGroups = 64;
+static_assert(kFuseGroups == 64, "one group per lane of a statistic's wave");
 constexpr int kFuseThreads = kNStat * kFuseGroups + 64;   // then one wave for L
 
 struct FuseArgs {
@@ -1699,16 +1671,15 @@ __global__ __launch_bounds__(kFuseThreads) void reduce_update_kernel(
 #pragma unroll
       for (int u = 0; u < 16; ++u) acc += v[u];
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    acc = wave_sum_f64(acc);
     if (lane == 0) tot[kNStat] = acc;
   }
-  // group g += group g + half for every statistic, half = G/2, ..., 1
-#pragma unroll
-  for (int half = kFuseGroups / 2; half > 0; half >>= 1) {
-    __syncthreads();
-    if (stats && tid < half * kNStat) sums[tid] += sums[tid + half * kNStat];
+  // wave s adds the G = 64 group sums of statistic s (lane g: group g)
+  __syncthreads();
+  if (stats && (tid >> 6) < kNStat) {
+    const double v = wave_sum_f64(sums[lane * kNStat + (tid >> 6)]);
+    if (lane == 0) tot[tid >> 6] = v;
   }
-  if (stats && tid < kNStat) tot[tid] = sums[tid];
   __syncthreads();
   if (lcol && tid == 0 && q.loglik_slot) {
     const double L = tot[kNStat];
