@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void em4_tile_kernel(
     }
   }
   double v = Lacc;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v = wave_sum_f64(v);
   if ((tid & 63) == 0) wL[tid >> 6] = v;
   __syncthreads();
   if (tid == 0) {
@@ -1205,7 +1205,7 @@ __global__ __launch_bounds__(NW * 64) void em4_cull_kernel(
     }
   }
   double v = Lacc;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v = wave_sum_f64(v);
   if (lane == 0) wL[tid >> 6] = v;
   __syncthreads();
   if (tid == 0) {

@@ -206,11 +206,11 @@ __device__ inline void apply_bound(int K, const double *sC, float *cpar,
   if (threadIdx.x == 0) *reinterpret_cast<double *>(cpar + (size_t)K * kParStride) = C;
 }
 
-// Block-wide reductions in a fixed order with two barriers: a butterfly in
+// Block-wide reductions in a fixed order with two barriers: a DPP wave sum in
 // each wave, then the wave results added in wave order by one thread.
 template <int NT>
 __device__ inline double block_sum_fast(double v, double *scratch) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v = wave_sum_f64(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -750,9 +750,9 @@ __attribute__((amdgpu_waves_per_eu(GMM_TILE_WPE, 8))) void em_tile_kernel(
       }
     }
   }
-  // block sum of the per-point log-normalisers (fixed butterfly order)
+  // block sum of the per-point log-normalisers (fixed order: DPP rows, then rows and waves in order)
   double v = Lacc;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v = wave_sum_f64(v);
   if ((tid & 63) == 0) wL[tid >> 6] = v;
   __syncthreads();
   if (tid == 0) {
@@ -1399,7 +1399,7 @@ __device__ __forceinline__ void cull_end(const CullLds &L, double *__restrict__ 
     }
   }
   double v = Lacc;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v = wave_sum_f64(v);
   if (lane == 0) L.wL[w] = v;
   __syncthreads();
   if (tid == 0) {
@@ -1941,7 +1941,7 @@ __global__ __launch_bounds__(BLOCK) void em_batch_kernel(
       }
     }
     double v = Lacc;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = wave_sum_f64(v);
     if ((tid & 63) == 0) wL[tid >> 6] = v;
     __syncthreads();
     if (tid == 0) {
@@ -2220,11 +2220,11 @@ __global__ __launch_bounds__(BLOCK) void em_bwd_kernel(
       row[j * K + i] = sum;
     }
   }
-  // block sums of lse and the six pose terms (fixed butterfly order)
+  // block sums of lse and the six pose terms (fixed order: DPP rows, then rows and waves in order)
   double vals[7] = {Lacc, pg[0], pg[1], pg[2], pg[3], pg[4], pg[5]};
   for (int k = 0; k < 7; ++k) {
     double v = vals[k];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = wave_sum_f64(v);
     if ((tid & 63) == 0) wL[k * (BLOCK / 64) + (tid >> 6)] = v;
   }
   __syncthreads();
