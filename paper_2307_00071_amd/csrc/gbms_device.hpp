@@ -21,7 +21,8 @@
 //     axis (4^D slots, lane = slot mod 64), so the cell that holds a point
 //     reaches the same lane whatever s is: the neighbourhood sum is then a
 //     function of the neighbourhood alone (each lane adds its cells' points
-//     in sorted order, rounds in order, then a fixed butterfly), and seeds
+//     in sorted order, rounds in order, then a fixed DPP reduction: within
+//     each 16-lane row, then the rows in order), and seeds
 //     that reach the same neighbourhood get bitwise the same mean;
 //   * the merge never sorts the modes: mode i is kept iff no kept mode that
 //     precedes it lies within h, so it needs only the predecessors within h
@@ -38,10 +39,13 @@
 #include <stdint.h>
 
 #include "radix_device.hpp"
+#include "wave_f64.hpp"
 
 #pragma clang fp contract(off)
 
 namespace gbms_dev {
+
+using namespace gmm_wave;
 
 using gmm_dev::kSortChunk;
 using gmm_dev::kSortItems;
@@ -436,11 +440,9 @@ __global__ __launch_bounds__(kMsThreads) void ms_shift_kernel(
         }
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
-      for (int j = 0; j < D; ++j) acc[j] = acc[j] + __shfl_xor(acc[j], off, 64);
-      in += __shfl_xor(in, off, 64);
-    }
+    for (int j = 0; j < D; ++j) acc[j] = wave_sum_f64(acc[j]);
+    in = wave_sum_i32(in);
     if (in == 0) break;   // uniform: every lane holds the same sums
     cnt = in;
     double d[D];
@@ -548,11 +550,9 @@ __global__ __launch_bounds__(kMsThreads) void ms_shift4_kernel(
         }
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
-      for (int j = 0; j < D; ++j) acc[j] = acc[j] + __shfl_xor(acc[j], off, 64);
-      in += __shfl_xor(in, off, 64);
-    }
+    for (int j = 0; j < D; ++j) acc[j] = wave_sum_f64(acc[j]);
+    in = wave_sum_i32(in);
     if (lane == 0) {
 #pragma unroll
       for (int j = 0; j < D; ++j) part[w][j] = acc[j];

@@ -45,4 +45,14 @@ __device__ __forceinline__ double2 half_sums_f64(double v) {
                       readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// The same for 32-bit integers (exact, so any order gives the same sum).
+__device__ __forceinline__ int wave_sum_i32(int v) {
+  v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true);
+  v += __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);
+  v += __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+  v += __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
+  return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+         (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
+}
+
 }  // namespace gmm_wave
