@@ -31,6 +31,8 @@
 
 #pragma once
 
+#include "em_device.hpp"
+
 namespace gmm_dev {
 
 constexpr int kSmallThreads = 256;     // block = tile = 256 points
